@@ -1,0 +1,248 @@
+/*
+ * bfs.h - C ABI of libbfs.so: level-synchronous breadth-first search and the
+ * local sparse-matrix x sparse-vector product (SpMSpV) of the 2D algorithm,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Bulu\c{c} and Madduri, "Parallel Breadth-First Search on
+ * Distributed Memory Systems"):
+ *   - BFS explores the graph one level at a time (section 2.1, Algorithm 1;
+ *     one synchronisation per level as in the PRAM formulation of section
+ *     2.2).
+ *   - Each level is the product x_{k+1} = A^T (x) x_k masked by the
+ *     complement of the visited set (section 3.2): a sparse-matrix x
+ *     sparse-vector product over a (select, min) semiring, with a dense
+ *     parents array standing in for the union of past frontiers.
+ *   - One process's share of the 2D decomposition (section 3.2, Eq. of the
+ *     2D partitioning; Algorithm 3) is a hypersparse block stored as DCSC
+ *     (section 4.1: IR row ids, CP column pointers, JC non-empty column
+ *     ids); its local product is bfs_spmspv (Algorithm 3, the SpMSV step;
+ *     section 4.2).
+ *
+ * Output convention (Algorithm 3): parent[v] is the predecessor of v on a
+ * shortest path from the root, -1 when unreachable; parent[root] = root.
+ * level[v] is the hop distance d(root, v) (Algorithm 1's d), -1 when
+ * unreachable. The semiring's "min" makes parent[v] the smallest vertex id
+ * among the neighbours of v one level closer to the root, so results are
+ * unique and deterministic.
+ *
+ * Conventions of every call:
+ *   - Returns a bfs_status code (0 = BFS_OK); never throws or aborts across
+ *     the ABI. bfs_last_error() gives a thread-local message for the last
+ *     failing call on the calling thread.
+ *   - Vertex ids and DCSC indices are int32 (ids < 2^31). CSR row offsets
+ *     are int32 or int64 at the caller's choice (stored as int64 on the
+ *     device).
+ *   - Input arrays are copied at create time: the library owns its device
+ *     copy, and the caller may free its arrays as soon as create returns.
+ *   - Output arrays are caller-owned. They are device pointers (e.g. a
+ *     PyTorch tensor's data_ptr()) unless stated otherwise; bfs_run also
+ *     accepts host pointers (filled by a copy on the same stream).
+ *   - Streams are hipStream_t passed as void* (NULL = the default stream).
+ *   - All calls on one graph handle must come from one host thread at a
+ *     time; a handle's device workspace is shared by its runs, so two runs on
+ *     one handle must not overlap on different streams.
+ */
+#ifndef BFS_MI355X_BFS_H
+#define BFS_MI355X_BFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bfs_graph bfs_graph_t;
+typedef struct bfs_server bfs_server_t;
+
+typedef enum bfs_status {
+  BFS_OK = 0,
+  BFS_ERR_ARG = -1,         /* bad argument (null handle, root out of range, ...) */
+  BFS_ERR_FORMAT = -2,      /* malformed CSR/DCSC rejected at create */
+  BFS_ERR_OOM = -3,         /* device or host allocation failed */
+  BFS_ERR_CAPACITY = -4,    /* output too small; required size reported */
+  BFS_ERR_DEVICE = -5,      /* HIP runtime or kernel error */
+  BFS_ERR_BUSY = -6,        /* handle has work in flight */
+  BFS_ERR_TIMEOUT = -7,     /* wait or server ticket timed out */
+  BFS_ERR_UNSUPPORTED = -8  /* size or mode outside what this build handles */
+} bfs_status_t;
+
+/* Flags for the create calls. */
+#define BFS_DEVICE_PTRS 0x1u  /* input arrays are device pointers */
+#define BFS_TRUSTED 0x2u      /* skip validation of the input arrays */
+
+/*
+ * Sparse vector with device storage, indices strictly ascending (the 2D
+ * algorithm's frontier is a sorted sparse vector, section 4.1).
+ *   nnz       number of entries (host value; set by bfs_spmspv on output)
+ *   capacity  entries that idx/val can hold (output vectors only)
+ *   idx       device int32[capacity], ascending
+ *   val       device int32[capacity]; for an input frontier it may be NULL,
+ *             meaning val(k) = k (the frontier vertex's own id is selected)
+ */
+typedef struct bfs_svec {
+  int64_t nnz;
+  int64_t capacity;
+  int32_t* idx;
+  int32_t* val;
+} bfs_svec_t;
+
+/* Statistics of the last completed run on a graph handle. */
+typedef struct bfs_run_stats {
+  int32_t depth;             /* largest level assigned (0 for an isolated root) */
+  int32_t levels;            /* levels expanded (levels with a non-empty input frontier) */
+  int64_t edges_traversed;   /* adjacencies scanned = sum of degrees of reached vertices */
+  int64_t reached;           /* vertices with level >= 0 */
+  int64_t frontier_total;    /* sum of frontier sizes over all levels */
+  int32_t expand_launches;   /* expand-kernel launches, including empty speculative ones */
+  int32_t pad;
+  double expand_ms;          /* summed device time of those launches (options.profile = 1) */
+  double total_ms;           /* device time of the whole run (options.profile = 1) */
+} bfs_run_stats_t;
+
+/* Run-time tuning knobs of a graph handle (0 = keep the current value). */
+typedef struct bfs_options {
+  int32_t mode;         /* 1 = one launch pair per level, 2 = persistent (one launch) */
+  int32_t batch_levels; /* levels enqueued between host checks in mode 1 */
+  int32_t grid_blocks;  /* blocks of the expand kernel */
+  int32_t lds_bitmap;   /* 1 = stage the visited bitmap in LDS when it fits */
+  int32_t profile;      /* 1 = time each expand launch with HIP events (-1 = off) */
+} bfs_options_t;
+
+/* ---------------------------------------------------------------- graphs */
+
+/*
+ * CSR graph with n vertices and nnz adjacencies (section 4.1, "Graph
+ * Representation": the adjacencies of vertex i are contiguous and sorted,
+ * row_offsets has n + 1 entries). offset_bytes is 4 or 8. For an undirected
+ * graph each edge appears in both rows; a directed CSR is traversed along
+ * its stored (outgoing) adjacencies.
+ * Validation (unless BFS_TRUSTED): row_offsets[0] = 0, non-decreasing,
+ * row_offsets[n] = nnz, every col_idx in [0, n). Adjacency order is not
+ * required for correctness. Fails with BFS_ERR_FORMAT when violated.
+ * 1 <= n < 2^31; nnz < 2^(64 - ceil(log2(n + 1))).
+ */
+int bfs_graph_create_csr(int64_t n, int64_t nnz, const void* row_offsets, int offset_bytes,
+                         const int32_t* col_idx, uint32_t flags, bfs_graph_t** out);
+
+/*
+ * Hypersparse block in DCSC (section 4.1): nzc non-empty columns with ids
+ * jc[0..nzc) strictly ascending, column pointers cp[0..nzc] (cp[0] = 0,
+ * strictly increasing, cp[nzc] = nnz) and row ids ir[0..nnz), each in
+ * [0, nrows). The entry A(r, k) != 0 means an edge from vertex k (column,
+ * the frontier side) to vertex r (row, the output side).
+ */
+int bfs_graph_create_dcsc(int32_t nrows, int32_t ncols, int32_t nzc, int64_t nnz,
+                          const int32_t* jc, const int32_t* cp, const int32_t* ir,
+                          uint32_t flags, bfs_graph_t** out);
+
+/* Releases a graph. BFS_ERR_BUSY while a server or batch still uses it. */
+int bfs_graph_destroy(bfs_graph_t* g);
+
+/* n (rows for a DCSC block), nnz and device bytes held by the handle. */
+int bfs_graph_info(const bfs_graph_t* g, int64_t* n, int64_t* nnz, int64_t* device_bytes);
+
+int bfs_graph_set_options(bfs_graph_t* g, const bfs_options_t* opt);
+int bfs_graph_get_options(const bfs_graph_t* g, bfs_options_t* opt);
+
+/* ---------------------------------------------------------------- BFS */
+
+/*
+ * BFS from `root` on a CSR graph (Algorithms 1 and 3). parent is required,
+ * level may be NULL; both hold n int32 and may be device or host memory.
+ * Synchronous: returns when the outputs are complete.
+ */
+int bfs_run(bfs_graph_t* g, int32_t root, int32_t* parent, int32_t* level);
+
+/*
+ * Same as bfs_run on `hip_stream`. In mode 2 (persistent) and for device
+ * outputs it enqueues work only and returns at once; in mode 1 it waits for
+ * level counts between batches of levels. Device errors are reported by the
+ * next synchronising call on the handle.
+ */
+int bfs_run_async(bfs_graph_t* g, int32_t root, int32_t* parent, int32_t* level,
+                  void* hip_stream);
+
+/* Statistics of the last completed run (synchronises the handle's stream). */
+int bfs_last_stats(bfs_graph_t* g, bfs_run_stats_t* st);
+
+/*
+ * Local product of one 2D share (Algorithm 3's SpMSV step, section 4.2):
+ *   out[r] = min{ val(k) : k in frontier, A(r, k) != 0 },
+ * emitted for every r whose set is non-empty, rows ascending. Entries of the
+ * frontier on empty columns contribute nothing. No visited mask is applied
+ * (the owner applies it, Algorithm 3). frontier->idx must be strictly
+ * ascending and in [0, ncols) (BFS_ERR_ARG otherwise, checked on device).
+ * When out->capacity is too small, returns BFS_ERR_CAPACITY with the
+ * required size in out->nnz and writes nothing to out->idx/val.
+ * Synchronous on `hip_stream` (reads the output count back).
+ */
+int bfs_spmspv(bfs_graph_t* block, const bfs_svec_t* frontier, bfs_svec_t* out,
+               void* hip_stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/*
+ * Runs `count` independent BFS queries (graphs[i], roots[i]) in one
+ * persistent launch (a multi-query kernel with per-query frontiers and level
+ * counters). parents[i] (required) and levels[i] (may be NULL) are device
+ * arrays of graphs[i]'s n. Results equal those of bfs_run for each query.
+ * Synchronous on `hip_stream`.
+ */
+int bfs_run_batch(int32_t count, bfs_graph_t* const* graphs, const int32_t* roots,
+                  int32_t* const* parents, int32_t* const* levels, void* hip_stream);
+
+/* ---------------------------------------------------------------- server */
+
+typedef struct bfs_server_config {
+  int32_t slots;            /* queries in flight at most (<= 4096) */
+  int64_t memory_budget;    /* device bytes for per-query state; 0 = 25% of free */
+  int32_t max_levels_step;  /* levels a query may advance per device step (0 = auto) */
+} bfs_server_config_t;
+
+typedef struct bfs_result {
+  int32_t status;         /* BFS_OK when done; BFS_ERR_BUSY while pending */
+  int32_t depth;
+  int64_t edges_traversed;
+  double t_arrive;        /* seconds, host monotonic clock */
+  double t_admit;
+  double t_done;
+} bfs_result_t;
+
+/*
+ * Continuous-batching server: queries are admitted while others run, as
+ * slots and device memory free up, and every active query advances inside
+ * the same device steps. parent/level are device arrays of the graph's n
+ * and must stay valid until the ticket completes.
+ */
+int bfs_server_create(const bfs_server_config_t* cfg, bfs_server_t** out);
+int bfs_server_submit(bfs_server_t* s, bfs_graph_t* g, int32_t root, int32_t* parent,
+                      int32_t* level, uint64_t* ticket);
+/* Non-blocking: fills *out; status BFS_ERR_BUSY while pending. */
+int bfs_server_poll(bfs_server_t* s, uint64_t ticket, bfs_result_t* out);
+/* Blocks until the ticket completes or timeout_s elapses (BFS_ERR_TIMEOUT). */
+int bfs_server_wait(bfs_server_t* s, uint64_t ticket, double timeout_s, bfs_result_t* out);
+/* Drives the server until every submitted query is done. */
+int bfs_server_drain(bfs_server_t* s);
+int bfs_server_destroy(bfs_server_t* s);
+
+/* ---------------------------------------------------------------- tuning */
+
+/*
+ * Times the expand-kernel launch shapes on this graph from a few roots and
+ * keeps the fastest in the handle's options; when cache_path is not NULL
+ * the choice is read from / appended to that file, keyed by device name and
+ * graph shape.
+ */
+int bfs_tune(bfs_graph_t* g, const char* cache_path);
+
+/* ---------------------------------------------------------------- misc */
+
+const char* bfs_last_error(void);
+/* Library version string. */
+const char* bfs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFS_MI355X_BFS_H */

@@ -1,0 +1,162 @@
+// Internal declarations shared by the library's translation units: the
+// graph handle, the per-run device state, wave64 helpers and the host-side
+// launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bfs.h"
+
+namespace bfsi {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define BFS_HIP(call)                                      \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return ::bfsi::hip_fail(e_, #call); \
+  } while (0)
+
+// ------------------------------------------------------------------ shapes
+// Expand kernel: 256 threads (4 waves of 64) own a tile of kTile
+// consecutive edges of the level's edge space.
+constexpr int kBlock = 256;
+constexpr int kItems = 4;
+constexpr int kTile = kBlock * kItems;
+
+enum GraphKind { kCsr = 1, kDcsc = 2 };
+
+// Per-run device state of the CSR path. ctr[k % 3] packs the frontier
+// produced by level k: (edge total << cbits) | vertex count.
+struct LevelState {
+  unsigned long long ctr[3];
+  int32_t k_expand;   // level the next expand launch processes
+  int32_t k_fold;     // level the next fold launch closes
+  int32_t depth;      // largest level assigned
+  int32_t levels;     // expand launches that found a non-empty frontier
+  unsigned long long edges;    // sum of frontier edge totals
+  unsigned long long reached;  // owners over the run (+1 for the root)
+  unsigned long long frontier_total;  // sum of frontier sizes
+  int32_t error;
+  int32_t pad;
+};
+
+struct CsrDev {
+  int64_t n = 0, nnz = 0;
+  int cbits = 0;                 // bits of the packed counter holding the count
+  int64_t* off = nullptr;        // n + 1
+  int32_t* col = nullptr;        // nnz
+  // workspace
+  uint32_t* vis = nullptr;       // visited bitmap, ceil(n / 32) words
+  int64_t nwords = 0;
+  int32_t* qv[2] = {nullptr, nullptr};   // frontier vertex ids
+  int64_t* qo[2] = {nullptr, nullptr};   // row start off[v] of each entry
+  int64_t* qe[2] = {nullptr, nullptr};   // exclusive edge prefix of each entry
+  int32_t* jstart = nullptr;     // first queue entry of each expand tile
+  int64_t njstart = 0;
+  LevelState* state = nullptr;
+  // host staging for host-pointer outputs
+  int32_t* tmp_parent = nullptr;
+  int32_t* tmp_level = nullptr;
+};
+
+struct DcscDev {
+  int32_t nrows = 0, ncols = 0, nzc = 0;
+  int64_t nnz = 0;
+  int32_t* jc = nullptr;
+  int32_t* cp = nullptr;
+  int32_t* ir = nullptr;
+  int aux_shift = 0;             // column bucket width = 2^aux_shift
+  int64_t naux = 0;
+  int32_t* aux = nullptr;        // aux[b] = first p with jc[p] >= b << aux_shift
+  // sparse accumulator (SPA): min values + occupied bitmap, kept clean
+  uint32_t* spa_val = nullptr;   // nrows, all 0xFFFFFFFF between calls
+  uint32_t* spa_occ = nullptr;   // ceil(nrows / 32) words, zero between calls
+  int64_t nwords = 0;
+  int64_t* blk_count = nullptr;  // per compaction block counts / offsets
+  int64_t nblk = 0;
+  unsigned long long* counters = nullptr;  // [0] out count, [1] error flag
+  unsigned long long* h_counters = nullptr;  // pinned host copy
+};
+
+}  // namespace bfsi
+
+struct bfs_graph {
+  int kind = 0;
+  int device = 0;
+  int64_t device_bytes = 0;
+  bfs_options_t opt{};
+  std::atomic<int> users{0};   // batch/server references
+  bfsi::CsrDev csr;
+  bfsi::DcscDev dcsc;
+  hipStream_t last_stream = nullptr;
+  unsigned long long* h_ctr = nullptr;   // pinned readback of one counter
+  bfs_run_stats_t last{};
+  int stats_valid = 0;
+  // profiling (options.profile = 1): one event pair per expand launch
+  std::vector<hipEvent_t> ev;
+  int expand_launches = 0;
+  int profiled = 0;
+};
+
+namespace bfsi {
+
+// ------------------------------------------------------------------ launchers
+// bfs_csr.hip
+int csr_alloc_workspace(bfs_graph* g);
+int csr_widen(const int32_t* d_src32, int64_t n1, int64_t* d_dst, hipStream_t s);
+void csr_free(bfs_graph* g);
+int csr_validate(bfs_graph* g, hipStream_t s);
+int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStream_t s,
+            bool sync);
+int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st);
+
+// bfs_dcsc.hip
+int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate);
+void dcsc_free(bfs_graph* g);
+int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t s);
+
+// ------------------------------------------------------------------ device helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __ballot(p); }
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int lanes_below(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ long long shfl_ll(long long v, int src) {
+  const int lo = __shfl((int)(v & 0xFFFFFFFF), src, 64);
+  const int hi = __shfl((int)(v >> 32), src, 64);
+  return ((long long)hi << 32) | (unsigned int)lo;
+}
+
+__device__ __forceinline__ long long shfl_up_ll(long long v, int d) {
+  const int lo = __shfl_up((int)(v & 0xFFFFFFFF), d, 64);
+  const int hi = __shfl_up((int)(v >> 32), d, 64);
+  return ((long long)hi << 32) | (unsigned int)lo;
+}
+
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ __forceinline__ long long wave_incl_scan(long long v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const long long t = shfl_up_ll(v, d);
+    if (l >= d) v += t;
+  }
+  return v;
+}
+
+}  // namespace bfsi

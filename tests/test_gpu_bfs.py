@@ -1,0 +1,206 @@
+"""GPU parity of bfs_run against the CPU oracle, bit for bit (integers)."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from gpu_helpers import assert_bfs_equal, gpu_bfs, graph_on_device, say, torch_cuda
+from paper_1104_4518_amd import bfs as B
+
+pytestmark = pytest.mark.gpu
+
+
+def test_rmat12_config_all_roots():
+    g = graphgen.config_graph("rmat12")
+    roots = graphgen.config_roots("rmat12", g)
+    G = graph_on_device(g)
+    for r in roots:
+        say(f"rmat12 root {r}")
+        _, ol = assert_bfs_equal(g, G, r)
+        st = G.last_stats()
+        assert st.edges_traversed == 2 * oracle.reached_edges(g, ol)
+        assert st.depth == ol.max()
+        assert st.reached == int((ol >= 0).sum())
+
+
+@pytest.mark.parametrize("name,edges,n", [
+    ("path", [(i, i + 1) for i in range(99)], 100),
+    ("star", [(0, i) for i in range(1, 300)], 300),
+    ("complete", [(i, j) for i in range(40) for j in range(i + 1, 40)], 40),
+    ("two_components", [(0, 1), (1, 2), (3, 4), (4, 5), (5, 3)], 8),
+    ("single_edge", [(0, 1)], 2),
+    ("isolated", [], 5),
+])
+def test_small_graphs_every_root(name, edges, n):
+    g = graphgen.from_edges(n, edges)
+    G = graph_on_device(g)
+    for r in range(n):
+        say(f"{name} root {r}")
+        assert_bfs_equal(g, G, r)
+
+
+def test_single_vertex():
+    g = graphgen.from_edges(1, [])
+    G = graph_on_device(g)
+    p, lv = gpu_bfs(G, 0)
+    assert p.tolist() == [0] and lv.tolist() == [0]
+
+
+@pytest.mark.parametrize("w", [33, 128])
+def test_grid_high_diameter(w):
+    g = graphgen.grid_csr(w)
+    G = graph_on_device(g)
+    for r in (0, w * w // 2 + 3, w * w - 1):
+        say(f"grid{w} root {r}")
+        assert_bfs_equal(g, G, r)
+
+
+def test_grid_512_corner():
+    g = graphgen.grid_csr(512)
+    G = graph_on_device(g)
+    say("grid512 root 0")
+    _, ol = assert_bfs_equal(g, G, 0)
+    assert ol.max() == 1022
+
+
+@pytest.mark.parametrize("scale,seed", [(14, 21), (16, 22), (18, 23)])
+def test_rmat_mid_scales(scale, seed):
+    g = graphgen.rmat_csr(scale, 16, seed)
+    G = graph_on_device(g)
+    for r in graphgen.roots(g, 4, 100 + seed):
+        say(f"rmat{scale} root {r}")
+        assert_bfs_equal(g, G, r, want_level=(r % 2 == 0))
+
+
+def test_er_graph():
+    g = graphgen.er_csr(16, 16, 7)
+    G = graph_on_device(g)
+    for r in graphgen.roots(g, 3, 77):
+        say(f"er16 root {r}")
+        assert_bfs_equal(g, G, r)
+
+
+def test_directed_csr_follows_stored_adjacencies():
+    rng = np.random.default_rng(3)
+    n = 3000
+    src = rng.integers(0, n, 20000)
+    dst = rng.integers(0, n, 20000)
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(np.bincount(src, minlength=n))
+    g = graphgen.CSR(n, off, dst.astype(np.int32))
+    G = graph_on_device(g)
+    for r in (0, 17, 2999):
+        say(f"directed root {r}")
+        assert_bfs_equal(g, G, r)
+
+
+def test_int32_offsets_and_device_inputs():
+    torch = torch_cuda()
+    g = graphgen.rmat_csr(12, 16, 9)
+    G32 = B.Graph.from_csr(g.n, g.off.astype(np.int32), g.col)
+    Gd = B.Graph.from_csr(g.n, torch.from_numpy(g.off).cuda(), torch.from_numpy(g.col).cuda())
+    Gd32 = B.Graph.from_csr(g.n, torch.from_numpy(g.off.astype(np.int32)).cuda(),
+                            torch.from_numpy(g.col).cuda())
+    r = int(graphgen.roots(g, 1, 5)[0])
+    for G in (G32, Gd, Gd32):
+        say(f"offsets variant root {r}")
+        assert_bfs_equal(g, G, r)
+
+
+def test_host_outputs():
+    g = graphgen.rmat_csr(12, 16, 1)
+    G = graph_on_device(g)
+    r = int(graphgen.roots(g, 1, 1000)[0])
+    parent = np.empty(g.n, np.int32)
+    level = np.empty(g.n, np.int32)
+    say("host outputs")
+    G.run(r, parent, level)
+    op, ol = oracle.bfs_graph(g, r)
+    assert np.array_equal(parent, op) and np.array_equal(level, ol)
+
+
+def test_stream_argument():
+    torch = torch_cuda()
+    g = graphgen.rmat_csr(13, 16, 4)
+    G = graph_on_device(g)
+    s = torch.cuda.Stream()
+    r = int(graphgen.roots(g, 1, 44)[0])
+    say("explicit stream")
+    with torch.cuda.stream(s):
+        p, lv = gpu_bfs(G, r, stream=s)
+    op, ol = oracle.bfs_graph(g, r)
+    assert np.array_equal(p, op) and np.array_equal(lv, ol)
+
+
+def test_launch_shapes_do_not_change_results():
+    """Schedule perturbation: grid sizes and host-check batching."""
+    g = graphgen.rmat_csr(15, 16, 31)
+    G = graph_on_device(g)
+    r = int(graphgen.roots(g, 1, 8)[0])
+    op, ol = oracle.bfs_graph(g, r)
+    for grid, batch in [(1, 1), (3, 2), (17, 16), (256, 1), (4096, 5)]:
+        G.set_options(grid_blocks=grid, batch_levels=batch)
+        say(f"grid {grid} batch {batch}")
+        p, lv = gpu_bfs(G, r)
+        assert np.array_equal(p, op) and np.array_equal(lv, ol), (grid, batch)
+    for rep in range(5):
+        p, lv = gpu_bfs(G, r)
+        assert np.array_equal(p, op) and np.array_equal(lv, ol)
+
+
+def test_profile_stats():
+    g = graphgen.rmat_csr(14, 16, 2)
+    G = graph_on_device(g)
+    G.set_options(profile=1)
+    r = int(graphgen.roots(g, 1, 2)[0])
+    gpu_bfs(G, r)
+    st = G.last_stats()
+    assert st.expand_launches >= st.levels >= 1
+    assert st.expand_ms > 0 and st.total_ms >= st.expand_ms
+
+
+def test_errors():
+    torch = torch_cuda()
+    g = graphgen.rmat_csr(10, 16, 1)
+    G = graph_on_device(g)
+    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    with pytest.raises(B.BfsError) as ei:
+        G.run(g.n, parent)
+    assert ei.value.code == B.BFS_ERR_ARG
+    with pytest.raises(B.BfsError):
+        G.run(-1, parent)
+    bad = g.col.copy()
+    bad[5] = g.n
+    with pytest.raises(B.BfsError) as ei:
+        B.Graph.from_csr(g.n, g.off, bad)
+    assert ei.value.code == B.BFS_ERR_FORMAT
+    off = g.off.copy()
+    off[3], off[4] = off[4], off[3] - 1
+    with pytest.raises(B.BfsError) as ei:
+        B.Graph.from_csr(g.n, off, g.col)
+    assert ei.value.code == B.BFS_ERR_FORMAT
+    off = g.off.copy()
+    off[-1] -= 1
+    with pytest.raises(B.BfsError) as ei:
+        B.Graph.from_csr(g.n, off, g.col)
+    assert ei.value.code == B.BFS_ERR_FORMAT
+    # the handle still works after the failed calls
+    r = int(graphgen.roots(g, 1, 3)[0])
+    assert_bfs_equal(g, G, r)
+
+
+def test_rmat22_config_sampled_roots():
+    """R-MAT scale 22 as benchmarked: full oracle on 3 roots, the definition
+    checker on 5 more."""
+    g = graphgen.config_graph("rmat22")
+    roots = graphgen.config_roots("rmat22", g)
+    G = graph_on_device(g, trusted=False)
+    for r in roots[:3]:
+        say(f"rmat22 root {r}")
+        assert_bfs_equal(g, G, r)
+    for r in roots[3:8]:
+        say(f"rmat22 checker root {r}")
+        p, lv = gpu_bfs(G, r)
+        assert oracle.check_bfs(g, int(r), p, lv) == (0, -1)

@@ -1,0 +1,126 @@
+"""GPU parity of bfs_spmspv (DCSC share) against the CPU oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from gpu_helpers import gpu_spmspv, say, torch_cuda
+from paper_1104_4518_amd import bfs as B
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fig3_dcsc.json")
+
+
+def block_on_device(b):
+    return B.Graph.from_dcsc(b.nrows, b.ncols, b.jc, b.cp, b.ir)
+
+
+def check(Gb, blk, fidx, fval=None):
+    gi, gv = gpu_spmspv(Gb, fidx, fval)
+    oi, ov = oracle.spmspv_block(blk, fidx, fval)
+    assert np.array_equal(gi, oi)
+    assert np.array_equal(gv, ov)
+    return gi
+
+
+def test_fig3_worked_example():
+    with open(GOLDEN) as f:
+        fx = json.load(f)
+    w = fx["whole"]
+    blk = graphgen.DCSCBlock(6, 6, np.array(w["jc"], np.int32), np.array(w["cp"], np.int32),
+                             np.array(w["ir"], np.int32))
+    Gb = block_on_device(blk)
+    for case in fx["products"]:
+        say(f"fig3 frontier {case['frontier']}")
+        gi, gv = gpu_spmspv(Gb, np.array(case["frontier"], np.int32))
+        assert gi.tolist() == case["out_idx"]
+        assert gv.tolist() == case["out_val"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_small_blocks(seed):
+    rng = np.random.default_rng(seed)
+    nr, nc = int(rng.integers(1, 3000)), int(rng.integers(1, 3000))
+    a = rng.random((nr, nc)) < float(rng.choice([0.0005, 0.003, 0.02]))
+    blk = graphgen.dcsc_from_dense(a)
+    Gb = block_on_device(blk)
+    for rep in range(3):
+        k = int(rng.integers(0, nc + 1))
+        f = np.sort(rng.choice(nc, size=k, replace=False)).astype(np.int32)
+        fv = rng.integers(-(1 << 30), 1 << 30, size=k).astype(np.int32) if rep == 2 else None
+        say(f"random block seed {seed} rep {rep} k {k}")
+        check(Gb, blk, f, fv)
+
+
+def test_edge_cases_and_errors():
+    a = np.zeros((70, 90), dtype=bool)
+    a[3, 5] = a[60, 5] = a[7, 89] = a[0, 40] = True
+    blk = graphgen.dcsc_from_dense(a)
+    Gb = block_on_device(blk)
+    say("empty frontier")
+    assert check(Gb, blk, np.zeros(0, np.int32)).size == 0
+    say("only empty columns")
+    assert check(Gb, blk, np.array([0, 1, 88], np.int32)).size == 0
+    say("max index")
+    check(Gb, blk, np.array([5, 89], np.int32))
+    # unsorted / duplicate / out-of-range frontier -> BFS_ERR_ARG
+    for bad in ([5, 3], [5, 5], [90], [-1, 5]):
+        say(f"bad frontier {bad}")
+        with pytest.raises(B.BfsError) as ei:
+            gpu_spmspv(Gb, np.array(bad, np.int32))
+        assert ei.value.code == B.BFS_ERR_ARG
+    # capacity too small -> BFS_ERR_CAPACITY with the size needed
+    say("capacity")
+    with pytest.raises(B.BfsError) as ei:
+        gpu_spmspv(Gb, np.array([5, 40, 89], np.int32), capacity=2)
+    assert ei.value.code == B.BFS_ERR_CAPACITY and "need 4" in str(ei.value)
+    # the accumulator is clean after the failures
+    check(Gb, blk, np.array([5, 40, 89], np.int32))
+    check(Gb, blk, np.arange(90, dtype=np.int32))
+
+
+def test_empty_block():
+    blk = graphgen.DCSCBlock(10, 10, np.zeros(0, np.int32), np.zeros(1, np.int32),
+                             np.zeros(0, np.int32))
+    Gb = block_on_device(blk)
+    assert check(Gb, blk, np.array([1, 2], np.int32)).size == 0
+
+
+def test_bad_dcsc_rejected():
+    jc = np.array([1, 1], np.int32)
+    cp = np.array([0, 1, 2], np.int32)
+    ir = np.array([0, 1], np.int32)
+    with pytest.raises(B.BfsError) as ei:
+        B.Graph.from_dcsc(4, 4, jc, cp, ir)
+    assert ei.value.code == B.BFS_ERR_FORMAT
+    with pytest.raises(B.BfsError) as ei:
+        B.Graph.from_dcsc(4, 4, np.array([1, 2], np.int32), cp, np.array([0, 4], np.int32))
+    assert ei.value.code == B.BFS_ERR_FORMAT
+
+
+@pytest.mark.parametrize("density", [0.0001, 0.001, 0.01, 0.1])
+def test_generated_block_scale20(density):
+    blk = graphgen.dcsc_block(20, 1 << 18, 12)
+    Gb = block_on_device(blk)
+    k = int(density * (1 << 20))
+    for s in range(2):
+        f = graphgen.frontier_sample(20, k, 300 + s)
+        say(f"block2^20 density {density} call {s}")
+        check(Gb, blk, f)
+
+
+def test_config_share_2pow26():
+    """The benchmarked share: 2^26 x 2^26, 16.8M uniform nonzeros, one call per
+    density and a repeat at 10% (the accumulator must reset between calls)."""
+    blk = graphgen.dcsc_block(26, 1 << 24, 4)
+    Gb = block_on_device(blk)
+    for i, density in enumerate([0.0001, 0.001, 0.01, 0.1, 0.1]):
+        k = int(density * (1 << 26))
+        f = graphgen.frontier_sample(26, k, 4000 + i)
+        say(f"share 2^26 density {density}")
+        out = check(Gb, blk, f)
+        assert out.size > 0

@@ -194,9 +194,11 @@ int bfs_run_batch(int32_t count, bfs_graph_t* const* graphs, const int32_t* root
 /* ---------------------------------------------------------------- server */
 
 typedef struct bfs_server_config {
-  int32_t slots;            /* queries in flight at most (<= 4096) */
-  int64_t memory_budget;    /* device bytes for per-query state; 0 = 25% of free */
-  int32_t max_levels_step;  /* levels a query may advance per device step (0 = auto) */
+  int32_t slots;            /* queries in flight at most, in [1, 4096] */
+  int64_t memory_budget;    /* device bytes for per-query frontier queues and bitmaps;
+                               0 = min(25% of free memory, 16 GiB) */
+  int32_t step_budget_us;   /* a device step stops advancing a query at the first level
+                               boundary after this many microseconds (0 = 400) */
 } bfs_server_config_t;
 
 typedef struct bfs_result {

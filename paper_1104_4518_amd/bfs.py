@@ -63,7 +63,7 @@ class Options(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("memory_budget", ctypes.c_int64),
-                ("max_levels_step", ctypes.c_int32)]
+                ("step_budget_us", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -91,6 +91,13 @@ def load(build_if_missing: bool = True):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime with the same soname as ROCm's. Loading
+    # torch first makes libbfs.so bind to that one runtime, so device memory
+    # and streams are shared and the process never holds two HIP runtimes.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         if not build_if_missing:
             raise RuntimeError(f"{LIB_PATH} is not built")
@@ -290,8 +297,8 @@ def run_batch(graphs: Sequence[Graph], roots, parents, levels=None, stream=None)
 class Server:
     """Continuous-batching BFS server (bfs_server_*)."""
 
-    def __init__(self, slots: int = 64, memory_budget: int = 0, max_levels_step: int = 0):
-        cfg = ServerConfig(slots, memory_budget, max_levels_step)
+    def __init__(self, slots: int = 64, memory_budget: int = 0, step_budget_us: int = 0):
+        cfg = ServerConfig(slots, memory_budget, step_budget_us)
         h = _vp()
         _check(load().bfs_server_create(ctypes.byref(cfg), ctypes.byref(h)), "bfs_server_create")
         self.handle = h.value

@@ -1,5 +1,93 @@
-// Batched multi-query BFS, continuous-batching server and launch-shape tuner.
-#include "bfs_internal.h"
+// bfs_run_batch: many independent BFS queries in one launch of the
+// multi-query kernel, and bfs_tune: picks expand-kernel launch shapes for a
+// graph by timing them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <unordered_set>
+#include <vector>
+
+#include "bfs_multi.h"
+
+namespace bfsi {
+namespace {
+
+// Device workspace shared by batch calls (grown on demand, kept until exit).
+struct BatchPool {
+  std::mutex mu;
+  int device = -1;
+  char* ws = nullptr;
+  int64_t ws_bytes = 0;
+  MQuery* d_qs = nullptr;
+  int32_t* d_order = nullptr;
+  int64_t q_cap = 0;
+  int32_t* d_counter = nullptr;
+  MQuery* h_qs = nullptr;
+  int32_t* h_order = nullptr;
+};
+
+BatchPool& pool() {
+  static BatchPool p;
+  return p;
+}
+
+int grow(BatchPool& p, int64_t nq, int64_t ws_need) {
+  if (nq > p.q_cap) {
+    (void)hipFree(p.d_qs);
+    (void)hipFree(p.d_order);
+    if (p.h_qs) (void)hipHostFree(p.h_qs);
+    if (p.h_order) (void)hipHostFree(p.h_order);
+    p.d_qs = nullptr;
+    p.d_order = nullptr;
+    p.h_qs = nullptr;
+    p.h_order = nullptr;
+    p.q_cap = 0;
+    const int64_t cap = std::max<int64_t>(nq, 1024);
+    BFS_HIP(hipMalloc(&p.d_qs, (size_t)cap * sizeof(MQuery)));
+    BFS_HIP(hipMalloc(&p.d_order, (size_t)cap * 4));
+    BFS_HIP(hipHostMalloc(&p.h_qs, (size_t)cap * sizeof(MQuery), hipHostMallocDefault));
+    BFS_HIP(hipHostMalloc(&p.h_order, (size_t)cap * 4, hipHostMallocDefault));
+    p.q_cap = cap;
+  }
+  if (!p.d_counter) BFS_HIP(hipMalloc(&p.d_counter, 4));
+  if (ws_need > p.ws_bytes) {
+    (void)hipFree(p.ws);
+    p.ws = nullptr;
+    p.ws_bytes = 0;
+    BFS_HIP(hipMalloc(&p.ws, (size_t)ws_need));
+    p.ws_bytes = ws_need;
+  }
+  return BFS_OK;
+}
+
+bool device_ptr(const void* ptr) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// Estimated cost of one query in ns: adjacency scans plus per-level latency.
+double query_cost(const bfs_graph* g) {
+  const double n = (double)g->csr.n, m = (double)g->csr.nnz;
+  const double edges = g->hint_edges > 0 ? (double)g->hint_edges : m;
+  double depth = (double)g->hint_depth;
+  if (depth <= 0) depth = (m / std::max(n, 1.0) < 6.0) ? 2.0 * std::sqrt(n) : 16.0;
+  return edges * 0.5 + depth * 4000.0;
+}
+
+}  // namespace
+}  // namespace bfsi
 
 using namespace bfsi;
 
@@ -7,32 +95,165 @@ extern "C" {
 
 int bfs_run_batch(int32_t count, bfs_graph_t* const* graphs, const int32_t* roots,
                   int32_t* const* parents, int32_t* const* levels, void* hip_stream) {
-  (void)count; (void)graphs; (void)roots; (void)parents; (void)levels; (void)hip_stream;
-  return fail(BFS_ERR_UNSUPPORTED, "not built yet");
+  try {
+    if (count < 0) return fail(BFS_ERR_ARG, "count must be >= 0");
+    if (count == 0) return BFS_OK;
+    if (!graphs || !roots || !parents) return fail(BFS_ERR_ARG, "NULL argument array");
+    std::unordered_set<const void*> outs;
+    int64_t nmax = 1;
+    for (int32_t i = 0; i < count; ++i) {
+      const bfs_graph* g = graphs[i];
+      if (!g || g->kind != kCsr) return fail(BFS_ERR_ARG, "batch query needs a CSR graph");
+      if (roots[i] < 0 || (int64_t)roots[i] >= g->csr.n)
+        return fail(BFS_ERR_ARG, "root out of range in batch");
+      if (!parents[i] || !device_ptr(parents[i]))
+        return fail(BFS_ERR_ARG, "batch parents must be device arrays");
+      if (!outs.insert(parents[i]).second) return fail(BFS_ERR_ARG, "batch outputs must not alias");
+      if (levels && levels[i]) {
+        if (!device_ptr(levels[i])) return fail(BFS_ERR_ARG, "batch levels must be device arrays");
+        if (!outs.insert(levels[i]).second)
+          return fail(BFS_ERR_ARG, "batch outputs must not alias");
+      }
+      nmax = std::max<int64_t>(nmax, g->csr.n);
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    BatchPool& p = pool();
+    std::lock_guard<std::mutex> lk(p.mu);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+
+    // workgroups: co-resident capacity, bounded by the queries and by a
+    // quarter of free memory for their workspaces
+    const int64_t ws_one = multi_ws_bytes(nmax);
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    int64_t grid = std::min<int64_t>(count, multi_grid(dev));
+    const int64_t mem_cap = std::max<int64_t>(1, (int64_t)(free_b + p.ws_bytes) / 4 / ws_one);
+    grid = std::max<int64_t>(1, std::min(grid, mem_cap));
+    int rc = grow(p, count, grid * ws_one);
+    if (rc != BFS_OK) return rc;
+
+    std::vector<std::pair<double, int32_t>> cost((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+      const bfs_graph* g = graphs[i];
+      MQuery& q = p.h_qs[i];
+      std::memset(&q, 0, sizeof(q));
+      q.off = g->csr.off;
+      q.col = g->csr.col;
+      q.parent = parents[i];
+      q.level = levels ? levels[i] : nullptr;
+      q.n = (int32_t)g->csr.n;
+      q.root = roots[i];
+      q.status = kQueryPending;
+      cost[(size_t)i] = {query_cost(g), i};
+    }
+    std::stable_sort(cost.begin(), cost.end(),
+                     [](const auto& a, const auto& b) { return a.first > b.first; });
+    for (int32_t i = 0; i < count; ++i) p.h_order[i] = cost[(size_t)i].second;
+
+    BFS_HIP(hipMemcpyAsync(p.d_qs, p.h_qs, (size_t)count * sizeof(MQuery),
+                           hipMemcpyHostToDevice, s));
+    BFS_HIP(hipMemcpyAsync(p.d_order, p.h_order, (size_t)count * 4, hipMemcpyHostToDevice, s));
+    rc = multi_reset_counter(p.d_counter, s);
+    if (rc != BFS_OK) return rc;
+    rc = multi_launch(p.d_qs, p.d_order, count, p.d_counter, (int)grid, true, 0ull, p.ws, ws_one,
+                      multi_q_bytes(nmax), s);
+    if (rc != BFS_OK) return rc;
+    BFS_HIP(hipMemcpyAsync(p.h_qs, p.d_qs, (size_t)count * sizeof(MQuery),
+                           hipMemcpyDeviceToHost, s));
+    BFS_HIP(hipStreamSynchronize(s));
+    for (int32_t i = 0; i < count; ++i) {
+      const MQuery& q = p.h_qs[i];
+      if (q.status != kQueryDone) return fail(BFS_ERR_DEVICE, "batch query did not complete");
+      bfs_graph* g = graphs[i];
+      g->hint_depth = std::max(g->hint_depth, q.depth);
+      g->hint_edges = std::max<int64_t>(g->hint_edges, (int64_t)q.edges);
+    }
+    return BFS_OK;
+  } catch (...) {
+    return fail(BFS_ERR_DEVICE, "exception in bfs_run_batch");
+  }
 }
 
-int bfs_server_create(const bfs_server_config_t* cfg, bfs_server_t** out) {
-  (void)cfg; (void)out;
-  return fail(BFS_ERR_UNSUPPORTED, "not built yet");
-}
-int bfs_server_submit(bfs_server_t* s, bfs_graph_t* g, int32_t root, int32_t* parent,
-                      int32_t* level, uint64_t* ticket) {
-  (void)s; (void)g; (void)root; (void)parent; (void)level; (void)ticket;
-  return fail(BFS_ERR_UNSUPPORTED, "not built yet");
-}
-int bfs_server_poll(bfs_server_t* s, uint64_t ticket, bfs_result_t* out) {
-  (void)s; (void)ticket; (void)out;
-  return fail(BFS_ERR_UNSUPPORTED, "not built yet");
-}
-int bfs_server_wait(bfs_server_t* s, uint64_t ticket, double timeout_s, bfs_result_t* out) {
-  (void)s; (void)ticket; (void)timeout_s; (void)out;
-  return fail(BFS_ERR_UNSUPPORTED, "not built yet");
-}
-int bfs_server_drain(bfs_server_t* s) { (void)s; return fail(BFS_ERR_UNSUPPORTED, "not built yet"); }
-int bfs_server_destroy(bfs_server_t* s) { (void)s; return fail(BFS_ERR_UNSUPPORTED, "not built yet"); }
 int bfs_tune(bfs_graph_t* g, const char* cache_path) {
-  (void)g; (void)cache_path;
-  return fail(BFS_ERR_UNSUPPORTED, "not built yet");
+  if (!g || g->kind != kCsr) return fail(BFS_ERR_ARG, "bfs_tune needs a CSR graph");
+  try {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    BFS_HIP(hipGetDeviceProperties(&prop, dev));
+    std::ostringstream key;
+    key << prop.gcnArchName << " n=" << g->csr.n << " nnz=" << g->csr.nnz;
+    if (cache_path) {
+      std::ifstream in(cache_path);
+      std::string line;
+      while (std::getline(in, line)) {
+        const size_t bar = line.find(" | ");
+        if (bar == std::string::npos || line.substr(0, bar) != key.str()) continue;
+        int grid = 0, batch = 0;
+        if (std::sscanf(line.c_str() + bar + 3, "grid=%d batch=%d", &grid, &batch) == 2 &&
+            grid > 0 && batch > 0) {
+          g->opt.grid_blocks = grid;
+          g->opt.batch_levels = batch;
+          return BFS_OK;
+        }
+      }
+    }
+    const int64_t n = g->csr.n;
+    int32_t *parent = nullptr, *level = nullptr;
+    BFS_HIP(hipMalloc(&parent, (size_t)n * 4));
+    BFS_HIP(hipMalloc(&level, (size_t)n * 4));
+    // roots: the three largest-degree vertices
+    std::vector<int64_t> off((size_t)std::min<int64_t>(n + 1, 1 << 22));
+    const int64_t probe = (int64_t)off.size() - 1;
+    BFS_HIP(hipMemcpy(off.data(), g->csr.off, off.size() * 8, hipMemcpyDeviceToHost));
+    std::vector<int32_t> cand;
+    for (int64_t v = 0; v < probe; ++v)
+      if (off[(size_t)v + 1] > off[(size_t)v]) cand.push_back((int32_t)v);
+    std::partial_sort(cand.begin(), cand.begin() + std::min<size_t>(3, cand.size()), cand.end(),
+                      [&](int32_t a, int32_t b) {
+                        return off[(size_t)a + 1] - off[(size_t)a] >
+                               off[(size_t)b + 1] - off[(size_t)b];
+                      });
+    cand.resize(std::min<size_t>(3, cand.size()));
+    if (cand.empty()) cand.push_back(0);
+    const bfs_options_t saved = g->opt;
+    const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    double best = 1e30;
+    int best_grid = saved.grid_blocks, best_batch = saved.batch_levels;
+    for (int per_cu : {2, 4, 6, 8}) {
+      for (int batch : {2, 4, 8}) {
+        g->opt.grid_blocks = cus * per_cu;
+        g->opt.batch_levels = batch;
+        int rc = csr_run(g, cand[0], parent, level, nullptr, true);   // warm
+        if (rc != BFS_OK) break;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int32_t r : cand) {
+          rc = csr_run(g, r, parent, level, nullptr, true);
+          if (rc != BFS_OK) break;
+        }
+        const double dt =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (rc == BFS_OK && dt < best) {
+          best = dt;
+          best_grid = g->opt.grid_blocks;
+          best_batch = batch;
+        }
+      }
+    }
+    (void)hipFree(parent);
+    (void)hipFree(level);
+    g->opt = saved;
+    g->opt.grid_blocks = best_grid;
+    g->opt.batch_levels = best_batch;
+    if (cache_path) {
+      std::ofstream out(cache_path, std::ios::app);
+      out << key.str() << " | grid=" << best_grid << " batch=" << best_batch << "\n";
+    }
+    return BFS_OK;
+  } catch (...) {
+    return fail(BFS_ERR_DEVICE, "exception in bfs_tune");
+  }
 }
 
 }  // extern "C"

@@ -62,16 +62,18 @@ __global__ void k_seed(const int64_t* __restrict__ off, int32_t root, int32_t* p
   st->edges = 0ull;
   st->reached = 1ull;
   st->frontier_total = 0ull;
+  st->zcnt[0] = st->zcnt[1] = st->zcnt[2] = 0u;
   st->error = 0;
 }
 
 template <int TILE>
 __global__ void k_fold(Queues q, LevelState* st, uint32_t* __restrict__ vis,
-                       int32_t* __restrict__ jstart, int cbits) {
+                       int32_t* __restrict__ jstart, const int32_t* __restrict__ zq, int cbits) {
   const int k = st->k_fold;
   const unsigned long long c = st->ctr[k % 3];
   const int64_t F = (int64_t)(c & ((1ull << cbits) - 1));
   const int64_t T = (int64_t)(c >> cbits);
+  const int64_t Z = (int64_t)st->zcnt[k % 3];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->k_expand = k + 1;
     if (F > 0) {
@@ -79,10 +81,14 @@ __global__ void k_fold(Queues q, LevelState* st, uint32_t* __restrict__ vis,
       st->frontier_total += (unsigned long long)F;
     }
   }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < Z; j += stride) {
+    const int32_t v = zq[j];
+    atomicOr(&vis[v >> 5], 1u << (v & 31));
+  }
   if (F == 0) return;
   const int32_t* __restrict__ qv = q.qv[k & 1];
   const int64_t* __restrict__ qe = q.qe[k & 1];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < F; j += stride) {
     const int32_t v = qv[j];
     atomicOr(&vis[v >> 5], 1u << (v & 31));
@@ -96,7 +102,8 @@ template <int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_expand(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const uint32_t* __restrict__ vis, int32_t* __restrict__ parent, int32_t* __restrict__ level,
-    Queues q, const int32_t* __restrict__ jstart, LevelState* st, int cbits) {
+    Queues q, const int32_t* __restrict__ jstart, int32_t* __restrict__ zq, LevelState* st,
+    int cbits) {
   constexpr int TILE = BLOCK * ITEMS;
   constexpr int WAVES = BLOCK / 64;
   __shared__ long long s_qe[TILE + 1];
@@ -114,7 +121,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   const int64_t F = (int64_t)(cin & cmask);
   const int64_t T = (int64_t)(cin >> cbits);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->ctr[(k + 1) % 3] = 0ull;   // output counter of level k + 1
+    st->ctr[(k + 1) % 3] = 0ull;   // output counters of level k + 1
+    st->zcnt[(k + 1) % 3] = 0u;
     st->k_fold = k;
     if (F > 0) st->levels = k;
   }
@@ -186,6 +194,14 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
           s_od[p] = deg;
           s_oo[p] = vo;
         }
+      }
+      // reached but nothing to expand (out-degree 0): fold(k) marks it visited
+      const unsigned long long mz = wave_ballot(own && deg == 0);
+      if (mz) {
+        unsigned int base = 0;
+        if (lane == 0) base = atomicAdd(&st->zcnt[k % 3], (unsigned int)__popcll(mz));
+        base = __shfl(base, 0, 64);
+        if (own && deg == 0) zq[base + lanes_below(mz)] = v;
       }
     }
     __syncthreads();
@@ -306,6 +322,7 @@ int csr_alloc_workspace(bfs_graph* g) {
     BFS_HIP(hipMalloc(&c.qe[b], (size_t)c.n * 8));
   }
   BFS_HIP(hipMalloc(&c.jstart, (size_t)c.njstart * 4));
+  BFS_HIP(hipMalloc(&c.zq, (size_t)c.n * 4));
   BFS_HIP(hipMalloc(&c.state, sizeof(LevelState)));
   BFS_HIP(hipMemset(c.state, 0, sizeof(LevelState)));
   g->device_bytes += std::max<int64_t>(c.nwords, 1) * 4 + 2 * c.n * 20 + c.njstart * 4 +
@@ -324,6 +341,7 @@ void csr_free(bfs_graph* g) {
     (void)hipFree(c.qe[b]);
   }
   (void)hipFree(c.jstart);
+  (void)hipFree(c.zq);
   (void)hipFree(c.state);
   (void)hipFree(c.tmp_parent);
   (void)hipFree(c.tmp_level);
@@ -398,7 +416,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   }
   const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache;
   const int gf = gf_cache;
-  k_fold<kTile><<<gf, 256, 0, s>>>(q, c.state, c.vis, c.jstart, c.cbits);
+  k_fold<kTile><<<gf, 256, 0, s>>>(q, c.state, c.vis, c.jstart, c.zq, c.cbits);
   BFS_HIP(hipGetLastError());
 
   const int batch = g->opt.batch_levels > 0 ? g->opt.batch_levels : 4;
@@ -418,9 +436,9 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
         BFS_HIP(hipEventRecord(g->ev[2 + 2 * k], s));
       }
       k_expand<kBlock, kItems><<<ge, kBlock, 0, s>>>(c.off, c.col, c.vis, d_parent, d_level, q,
-                                                     c.jstart, c.state, c.cbits);
+                                                     c.jstart, c.zq, c.state, c.cbits);
       if (prof) BFS_HIP(hipEventRecord(g->ev[3 + 2 * k], s));
-      k_fold<kTile><<<gf, 256, 0, s>>>(q, c.state, c.vis, c.jstart, c.cbits);
+      k_fold<kTile><<<gf, 256, 0, s>>>(q, c.state, c.vis, c.jstart, c.zq, c.cbits);
       ++k;
     }
     BFS_HIP(hipGetLastError());

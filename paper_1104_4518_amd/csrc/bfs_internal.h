@@ -46,8 +46,10 @@ struct LevelState {
   unsigned long long edges;    // sum of frontier edge totals
   unsigned long long reached;  // owners over the run (+1 for the root)
   unsigned long long frontier_total;  // sum of frontier sizes
+  // vertices reached at level k with no outgoing adjacency (directed graphs):
+  // not expanded, but still marked visited by fold(k)
+  unsigned int zcnt[3];
   int32_t error;
-  int32_t pad;
 };
 
 struct CsrDev {
@@ -61,6 +63,7 @@ struct CsrDev {
   int32_t* qv[2] = {nullptr, nullptr};   // frontier vertex ids
   int64_t* qo[2] = {nullptr, nullptr};   // row start off[v] of each entry
   int64_t* qe[2] = {nullptr, nullptr};   // exclusive edge prefix of each entry
+  int32_t* zq = nullptr;         // reached vertices of out-degree 0 (per level)
   int32_t* jstart = nullptr;     // first queue entry of each expand tile
   int64_t njstart = 0;
   LevelState* state = nullptr;
@@ -106,6 +109,9 @@ struct bfs_graph {
   std::vector<hipEvent_t> ev;
   int expand_launches = 0;
   int profiled = 0;
+  // cost hints for ordering queries in batches (from earlier runs)
+  int32_t hint_depth = 0;
+  int64_t hint_edges = 0;
 };
 
 namespace bfsi {

@@ -84,7 +84,20 @@ def main() -> int:
     ap.add_argument("--workload", default="rmat22", choices=["rmat12", "rmat22", "rmat26", "er26"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (3 times), to scale HBM counters")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                          "repeats": 3}), flush=True)
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "

@@ -95,7 +95,7 @@ def test_server_timeout_busy_and_errors():
 
 
 def test_server_budget_too_small_rejected():
-    g = graphgen.grid_csr(300)
+    g = graphgen.grid_csr(600)     # 2.9 MB of workspace > the 1 MiB budget
     G = graph_on_device(g)
     torch = torch_cuda()
     S = B.Server(slots=2, memory_budget=1 << 20)

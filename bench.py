@@ -12,7 +12,13 @@ The JSON line also carries:
                 launch / average launch duration, both from HIP events
                 recorded around every expand launch on its stream
   cpu_baseline  the CPU oracle (serial C) timed on a bounded sample of roots
-  bfs_roofline  whole-BFS algorithmic bytes / BFS time, per root
+  bfs_roofline_frac  whole-BFS algorithmic bytes / BFS time, per root
+  spmspv        the 2D share (2^26 x 2^26 DCSC, 2^24 uniform nonzeros): 200
+                local products, 50 at each frontier density, p50 per density
+  mix           1024 queries over R-MAT scales 14-22 and 512^2 / 2048^2
+                grids: one-at-a-time plain path, one batched launch, and the
+                continuous-batching server under Poisson arrivals at 0.5x and
+                4x the plain path's capacity (GTEPS, p50/p99 latency)
 """
 from __future__ import annotations
 
@@ -47,9 +53,31 @@ def bfs_bytes(n: int, edges: int, reached: int) -> float:
     return 4.125 * edges + 24.0 * reached + 8.0 * n + n / 4.0
 
 
+def profiled_traffic(workload: str):
+    """HBM bytes per expand launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    prof = os.path.join(ROOT, "profiles", f"k_expand_{workload}.md")
+    src = os.path.join(ROOT, "paper_1104_4518_amd", "csrc", "bfs_csr.hip")
+    try:
+        text = open(prof).read()
+        want = re.search(r"source_sha256_16:\s*([0-9a-f]+)", text).group(1)
+        val = float(re.search(r"traffic_bytes_per_launch:\s*([0-9.]+)", text).group(1))
+        have = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except (OSError, AttributeError, ValueError):
+        return None
+    return val if have == want else None
+
+
 def harmonic(xs):
     xs = [x for x in xs if x > 0]
     return len(xs) / sum(1.0 / x for x in xs) if xs else 0.0
+
+
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else 0.0
 
 
 def cpu_baseline(g, roots, budget_s: float):
@@ -76,6 +104,234 @@ def cpu_baseline(g, roots, budget_s: float):
     }
 
 
+# ------------------------------------------------------------------ BFS leg
+def bfs_leg(args, torch, graphgen, B):
+    t0 = time.time()
+    log(f"generating {args.workload}")
+    g = graphgen.config_graph(args.workload)
+    roots = graphgen.config_roots(args.workload, g)
+    log(f"graph n={g.n} nnz={g.nnz} in {time.time() - t0:.1f}s; {len(roots)} roots")
+    G = B.Graph.from_csr(g.n, g.off, g.col, trusted=True)
+    G.set_options(profile=1)
+    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    level = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    log("graph resident on device")
+
+    for i in range(args.warmup):
+        G.run(int(roots[i % len(roots)]), parent, level)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    stats = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        r = int(roots[i % len(roots)])
+        starts[i].record()
+        G.run(r, parent, level)
+        ends[i].record()
+        stats.append(G.last_stats())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+
+    per_root_gteps, per_root_frac = [], []
+    exp_bytes = exp_ms = 0.0
+    exp_launches = 0
+    for i, st in enumerate(stats):
+        ms = starts[i].elapsed_time(ends[i])
+        m_r = st.edges_traversed // 2
+        per_root_gteps.append(m_r / (ms * 1e-3) / 1e9)
+        per_root_frac.append(bfs_bytes(g.n, st.edges_traversed, st.reached) / (ms * 1e-3) / 1e9
+                             / HBM_PEAK_GBS)
+        exp_bytes += expand_bytes(st.edges_traversed, st.frontier_total, st.reached)
+        exp_ms += st.expand_ms
+        exp_launches += st.expand_launches
+    value = harmonic(per_root_gteps)
+    achieved = exp_bytes / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else 0.0
+    log(f"timed {args.steps} roots in {wall:.3f}s wall; {value:.2f} GTEPS; expand "
+        f"{exp_launches} launches avg {exp_ms / max(exp_launches, 1) * 1e3:.1f} us")
+    res = {
+        "value": value,
+        "wall": wall,
+        "config": {
+            "workload": args.workload,
+            "n": g.n,
+            "adjacencies": g.nnz,
+            "edgefactor": 16,
+            "roots": len(roots),
+            "graph_hash": hex(g.hash()),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_expand",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": profiled_traffic(args.workload),
+            "launches": exp_launches,
+            "avg_launch_us": round(exp_ms / max(exp_launches, 1) * 1e3, 3),
+            "bytes_per_launch": round(exp_bytes / max(exp_launches, 1), 1),
+        },
+        "bfs_roofline_frac": round(harmonic(per_root_frac), 4),
+        "ms_per_bfs_p50": round(pct([starts[i].elapsed_time(ends[i]) for i in
+                                     range(args.steps)], 50), 4),
+    }
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline")
+        cpu = cpu_baseline(g, roots[:args.steps], args.cpu_budget)
+    del G
+    return res, cpu
+
+
+# ------------------------------------------------------------------ SpMSpV leg
+def spmspv_leg(torch, graphgen, B, np):
+    t0 = time.time()
+    blk = graphgen.dcsc_block(26, 1 << 24, 4)
+    log(f"share 2^26 x 2^26: nnz={blk.nnz} nzc={blk.nzc} in {time.time() - t0:.1f}s")
+    Gb = B.Graph.from_dcsc(blk.nrows, blk.ncols, blk.jc, blk.cp, blk.ir, trusted=True)
+    cap = blk.nnz
+    oi = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ov = torch.empty(cap, dtype=torch.int32, device="cuda")
+    colnnz = np.diff(blk.cp).astype(np.int64)
+    out = {}
+    call = 0
+    for density in (0.0001, 0.001, 0.01, 0.1):
+        k = int(density * (1 << 26))
+        times, algo, edges_s = [], [], []
+        for rep in range(51):
+            f = graphgen.frontier_sample(26, k, 1003 + call)
+            call += 1
+            fd = torch.from_numpy(f).cuda()
+            # per-call algorithmic work from the inputs (host numpy)
+            pos = np.searchsorted(blk.jc, f)
+            pos_c = np.minimum(pos, blk.nzc - 1)
+            hit = (pos < blk.nzc) & (blk.jc[pos_c] == f)
+            hits = int(hit.sum())
+            e = int(colnnz[pos_c[hit]].sum())
+            torch.cuda.synchronize()
+            s, t = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            cnt = Gb.spmspv(fd, k, oi, ov, cap)
+            t.record()
+            torch.cuda.synchronize()
+            if rep == 0:
+                continue              # first call of each density is a warm-up
+            us = s.elapsed_time(t) * 1e3
+            times.append(us)
+            algo.append(8.0 * k + 8.0 * hits + 4.0 * e + 8.0 * cnt)
+            edges_s.append(e / (us * 1e-6))
+        p50 = pct(times, 50)
+        frac = (float(np.median(algo)) / (p50 * 1e-6) / 1e9) / HBM_PEAK_GBS
+        out[f"{density * 100:g}%"] = {
+            "frontier": k,
+            "p50_us": round(p50, 2),
+            "p99_us": round(pct(times, 99), 2),
+            "edges_per_s": round(float(np.median(edges_s)), 1),
+            "roofline_frac": round(frac, 4) if density >= 0.01 else None,
+        }
+        log(f"spmspv {density * 100:g}%: p50 {p50:.1f} us")
+    del Gb
+    return out
+
+
+# ------------------------------------------------------------------ mix leg
+def mix_leg(torch, graphgen, B, np, nq: int):
+    t0 = time.time()
+    specs = [("rmat14", lambda: graphgen.rmat_csr(14, 16, 5)),
+             ("rmat16", lambda: graphgen.rmat_csr(16, 16, 5)),
+             ("rmat18", lambda: graphgen.rmat_csr(18, 16, 5)),
+             ("rmat20", lambda: graphgen.rmat_csr(20, 16, 5)),
+             ("rmat22", lambda: graphgen.rmat_csr(22, 16, 5)),
+             ("grid512", lambda: graphgen.grid_csr(512)),
+             ("grid2048", lambda: graphgen.grid_csr(2048))]
+    graphs, devs, cand = [], [], []
+    for name, mk in specs:
+        g = mk()
+        g.name = name
+        graphs.append(g)
+        devs.append(B.Graph.from_csr(g.n, g.off, g.col, trusted=True))
+        cand.append(np.nonzero(np.diff(g.off) > 0)[0].astype(np.int32))
+    log(f"mix graphs ready in {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(1004)
+    qg = rng.integers(0, len(graphs), nq)
+    qr = np.array([cand[i][rng.integers(0, cand[i].size)] for i in qg], np.int32)
+
+    # plain path, one query at a time (closed loop)
+    bufs = [(torch.empty(g.n, dtype=torch.int32, device="cuda"),
+             torch.empty(g.n, dtype=torch.int32, device="cuda")) for g in graphs]
+    for i in range(min(14, nq)):
+        devs[qg[i]].run(int(qr[i]), *bufs[qg[i]])
+    torch.cuda.synchronize()
+    edges = np.zeros(nq, np.int64)
+    t1 = time.perf_counter()
+    for i in range(nq):
+        G = devs[qg[i]]
+        G.run(int(qr[i]), *bufs[qg[i]])
+        edges[i] = G.last_stats().edges_traversed // 2
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t1
+    m_total = float(edges.sum())
+    plain = {"gteps": round(m_total / plain_s / 1e9, 4), "seconds": round(plain_s, 4),
+             "qps": round(nq / plain_s, 2)}
+    log(f"plain: {plain}")
+    del bufs
+
+    # per-query outputs for the batched and served runs
+    outs = [(torch.empty(graphs[i].n, dtype=torch.int32, device="cuda"),
+             torch.empty(graphs[i].n, dtype=torch.int32, device="cuda")) for i in qg]
+    B.run_batch([devs[i] for i in qg[:32]], qr[:32], [o[0] for o in outs[:32]],
+                [o[1] for o in outs[:32]])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    B.run_batch([devs[i] for i in qg], qr, [o[0] for o in outs], [o[1] for o in outs])
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t1
+    batched = {"gteps": round(m_total / batch_s / 1e9, 4), "seconds": round(batch_s, 4),
+               "speedup_vs_plain": round(plain_s / batch_s, 2)}
+    log(f"batched: {batched}")
+
+    served = {}
+    cap_qps = nq / plain_s
+    for factor in (0.5, 4.0):
+        qps = factor * cap_qps
+        arrivals = graphgen.poisson_arrivals(nq, qps, 2000 + int(factor * 10))
+        S = B.Server(slots=512)
+        tickets = []
+        t_base = time.perf_counter()
+        for i in range(nq):
+            while time.perf_counter() - t_base < arrivals[i]:
+                pass
+            tickets.append(S.submit(devs[qg[i]], int(qr[i]), outs[i][0], outs[i][1]))
+        S.drain()
+        res = [S.poll(t) for t in tickets]
+        S.destroy()
+        lat = [(r.t_done - r.t_arrive) * 1e3 for r in res]
+        span = max(r.t_done for r in res) - min(r.t_arrive for r in res)
+        m_served = float(sum(r.edges_traversed for r in res)) / 2
+        served[f"{factor:g}x"] = {
+            "qps": round(qps, 2),
+            "gteps": round(m_served / span / 1e9, 4),
+            "p50_ms": round(pct(lat, 50), 3),
+            "p99_ms": round(pct(lat, 99), 3),
+            "span_s": round(span, 3),
+        }
+        log(f"served {factor}x: {served[f'{factor:g}x']}")
+    # spot check: batched/served outputs equal a plain run of the same query
+    ok = True
+    for i in range(0, nq, 97):
+        p = torch.empty(graphs[qg[i]].n, dtype=torch.int32, device="cuda")
+        lv = torch.empty_like(p)
+        devs[qg[i]].run(int(qr[i]), p, lv)
+        torch.cuda.synchronize()
+        ok &= bool(torch.equal(p, outs[i][0]) and torch.equal(lv, outs[i][1]))
+    del outs, devs
+    return {"queries": nq, "graphs": [s[0] for s in specs], "plain": plain,
+            "batched": batched, "served": served, "spot_check_equal": ok}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +340,9 @@ def main() -> int:
     ap.add_argument("--workload", default="rmat22", choices=["rmat12", "rmat22", "rmat26", "er26"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--legs", default="bfs,spmspv,mix",
+                    help="comma list of legs to run: bfs, spmspv, mix")
+    ap.add_argument("--mix-queries", type=int, default=1024)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -114,92 +373,33 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    legs = set(args.legs.split(","))
 
-    t0 = time.time()
-    log(f"generating {args.workload}")
-    g = graphgen.config_graph(args.workload)
-    roots = graphgen.config_roots(args.workload, g)
-    log(f"graph n={g.n} nnz={g.nnz} in {time.time() - t0:.1f}s; {len(roots)} roots")
-    G = B.Graph.from_csr(g.n, g.off, g.col, trusted=True)
-    G.set_options(profile=1)
-    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    level = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    log("graph resident on device")
-
-    for i in range(args.warmup):
-        G.run(int(roots[i % len(roots)]), parent, level)
-    torch.cuda.synchronize()
-    log("warmup done")
-
-    per_root_gteps, per_root_frac = [], []
-    exp_bytes = exp_ms = 0.0
-    exp_launches = 0
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    stats = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        r = int(roots[i % len(roots)])
-        starts[i].record()
-        G.run(r, parent, level)
-        ends[i].record()
-        stats.append(G.last_stats())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-
-    for i, st in enumerate(stats):
-        ms = starts[i].elapsed_time(ends[i])
-        m_r = st.edges_traversed // 2
-        per_root_gteps.append(m_r / (ms * 1e-3) / 1e9)
-        per_root_frac.append(bfs_bytes(g.n, st.edges_traversed, st.reached) / (ms * 1e-3) / 1e9
-                             / HBM_PEAK_GBS)
-        exp_bytes += expand_bytes(st.edges_traversed, st.frontier_total, st.reached)
-        exp_ms += st.expand_ms
-        exp_launches += st.expand_launches
-    value = harmonic(per_root_gteps)
-    achieved = exp_bytes / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else 0.0
-    log(f"timed {args.steps} roots in {wall:.3f}s wall; {value:.2f} GTEPS; expand "
-        f"{exp_launches} launches avg {exp_ms / max(exp_launches, 1) * 1e3:.1f} us")
-
+    res, cpu = bfs_leg(args, torch, graphgen, B)
     out = {
         "metric": METRIC,
-        "value": round(value, 4),
+        "value": round(res["value"], 4),
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "ms_per_step": round(res["wall"] * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {
-            "workload": args.workload,
-            "n": g.n,
-            "adjacencies": g.nnz,
-            "edgefactor": 16,
-            "roots": len(roots),
-            "graph_hash": hex(g.hash()),
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_expand",
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "launches": exp_launches,
-            "avg_launch_us": round(exp_ms / max(exp_launches, 1) * 1e3, 3),
-            "bytes_per_launch": round(exp_bytes / max(exp_launches, 1), 1),
-        },
-        "bfs_roofline_frac": round(harmonic(per_root_frac), 4),
+        "config": res["config"],
+        "roofline": res["roofline"],
+        "bfs_roofline_frac": res["bfs_roofline_frac"],
+        "ms_per_bfs_p50": res["ms_per_bfs_p50"],
     }
-    if not args.no_cpu:
-        log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(g, roots[:args.steps], args.cpu_budget)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    if "spmspv" in legs:
+        out["spmspv"] = spmspv_leg(torch, graphgen, B, np)
+    if "mix" in legs:
+        out["mix"] = mix_leg(torch, graphgen, B, np, args.mix_queries)
     print(json.dumps(out), flush=True)
     return 0
 

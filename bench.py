@@ -111,7 +111,7 @@ def bfs_leg(args, torch, graphgen, B):
     g = graphgen.config_graph(args.workload)
     roots = graphgen.config_roots(args.workload, g)
     log(f"graph n={g.n} nnz={g.nnz} in {time.time() - t0:.1f}s; {len(roots)} roots")
-    G = B.Graph.from_csr(g.n, g.off, g.col, trusted=True)
+    G = B.Graph.from_csr(g.n, g.off, g.col, trusted=True, symmetric=True)
     G.set_options(profile=1)
     parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
     level = torch.empty(g.n, dtype=torch.int32, device="cuda")
@@ -252,7 +252,7 @@ def mix_leg(torch, graphgen, B, np, nq: int):
         g = mk()
         g.name = name
         graphs.append(g)
-        devs.append(B.Graph.from_csr(g.n, g.off, g.col, trusted=True))
+        devs.append(B.Graph.from_csr(g.n, g.off, g.col, trusted=True, symmetric=True))
         cand.append(np.nonzero(np.diff(g.off) > 0)[0].astype(np.int32))
     log(f"mix graphs ready in {time.time() - t0:.1f}s")
     rng = np.random.default_rng(1004)

@@ -69,6 +69,9 @@ typedef enum bfs_status {
 /* Flags for the create calls. */
 #define BFS_DEVICE_PTRS 0x1u  /* input arrays are device pointers */
 #define BFS_TRUSTED 0x2u      /* skip validation of the input arrays */
+#define BFS_SYMMETRIC 0x4u    /* CSR: caller asserts an undirected graph (every edge in both
+                                 rows) with ascending adjacency lists; without this flag and
+                                 without BFS_TRUSTED the library checks it at create */
 
 /*
  * Sparse vector with device storage, indices strictly ascending (the 2D
@@ -94,7 +97,7 @@ typedef struct bfs_run_stats {
   int64_t reached;           /* vertices with level >= 0 */
   int64_t frontier_total;    /* sum of frontier sizes over all levels */
   int32_t expand_launches;   /* expand-kernel launches, including empty speculative ones */
-  int32_t pad;
+  int32_t mark_levels;       /* levels resolved by mark-and-resolve instead of atomicMin */
   double expand_ms;          /* summed device time of those launches (options.profile = 1) */
   double total_ms;           /* device time of the whole run (options.profile = 1) */
 } bfs_run_stats_t;
@@ -106,6 +109,11 @@ typedef struct bfs_options {
   int32_t grid_blocks;  /* blocks of the expand kernel */
   int32_t lds_bitmap;   /* 1 = stage the visited bitmap in LDS when it fits */
   int32_t profile;      /* 1 = time each expand launch with HIP events (-1 = off) */
+  int32_t claim;        /* how a level resolves its new vertices' parents:
+                           3 = by frontier size (default), 1 = atomicMin claims always,
+                           2 = mark-and-resolve whenever the graph is symmetric */
+  int32_t claim_threshold; /* frontier edges from which a level uses mark-and-resolve
+                              (0 = keep; default max(n / 64, 4096)) */
 } bfs_options_t;
 
 /* ---------------------------------------------------------------- graphs */
@@ -166,6 +174,13 @@ int bfs_run_async(bfs_graph_t* g, int32_t root, int32_t* parent, int32_t* level,
 int bfs_last_stats(bfs_graph_t* g, bfs_run_stats_t* st);
 
 /*
+ * Device time of each expand launch of the last run, in launch order (level
+ * 1, 2, ...), when options.profile = 1. Writes min(capacity, launches)
+ * values to ms and the launch count to *count.
+ */
+int bfs_last_level_times(bfs_graph_t* g, double* ms, int32_t capacity, int32_t* count);
+
+/*
  * Local product of one 2D share (Algorithm 3's SpMSV step, section 4.2):
  *   out[r] = min{ val(k) : k in frontier, A(r, k) != 0 },
  * emitted for every r whose set is non-empty, rows ascending. Entries of the
@@ -199,6 +214,10 @@ typedef struct bfs_server_config {
                                0 = min(25% of free memory, 16 GiB) */
   int32_t step_budget_us;   /* a device step stops advancing a query at the first level
                                boundary after this many microseconds (0 = 400) */
+  int64_t large_query_nnz;  /* queries on graphs with at least this many adjacencies and an
+                               average degree >= 8 run one at a time across the whole GPU on
+                               a second stream instead of in the multi-query steps
+                               (0 = 2^23, -1 = never) */
 } bfs_server_config_t;
 
 typedef struct bfs_result {

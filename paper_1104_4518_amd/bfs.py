@@ -32,6 +32,7 @@ BFS_ERR_UNSUPPORTED = -8
 
 BFS_DEVICE_PTRS = 0x1
 BFS_TRUSTED = 0x2
+BFS_SYMMETRIC = 0x4
 
 _NAMES = {v: k for k, v in globals().items() if k.startswith("BFS_ERR_") or k == "BFS_OK"}
 
@@ -51,19 +52,20 @@ class RunStats(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("edges_traversed", ctypes.c_int64), ("reached", ctypes.c_int64),
                 ("frontier_total", ctypes.c_int64), ("expand_launches", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("expand_ms", ctypes.c_double),
+                ("mark_levels", ctypes.c_int32), ("expand_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch_levels", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("lds_bitmap", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("claim", ctypes.c_int32),
+                ("claim_threshold", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("memory_budget", ctypes.c_int64),
-                ("step_budget_us", ctypes.c_int32)]
+                ("step_budget_us", ctypes.c_int32), ("large_query_nnz", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):
@@ -117,6 +119,8 @@ def load(build_if_missing: bool = True):
         "bfs_run": [_vp, _i32, _vp, _vp],
         "bfs_run_async": [_vp, _i32, _vp, _vp, _vp],
         "bfs_last_stats": [_vp, ctypes.POINTER(RunStats)],
+        "bfs_last_level_times": [_vp, ctypes.POINTER(ctypes.c_double), _i32,
+                                 ctypes.POINTER(_i32)],
         "bfs_spmspv": [_vp, ctypes.POINTER(SVec), ctypes.POINTER(SVec), _vp],
         "bfs_run_batch": [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_i32), ctypes.POINTER(_vp),
                           ctypes.POINTER(_vp), _vp],
@@ -186,7 +190,10 @@ class Graph:
 
     # ---------------------------------------------------------------- create
     @classmethod
-    def from_csr(cls, n: int, off, col, trusted: bool = False) -> "Graph":
+    def from_csr(cls, n: int, off, col, trusted: bool = False,
+                 symmetric: Optional[bool] = None) -> "Graph":
+        """symmetric=True asserts an undirected graph with ascending rows;
+        None lets the library check it (unless trusted)."""
         lib = load()
         dev = _is_device(off)
         if dev != _is_device(col):
@@ -198,11 +205,16 @@ class Graph:
         if ob == 4 and not str(off.dtype).endswith("int32"):
             raise TypeError("row offsets must be int32 or int64")
         flags = (BFS_DEVICE_PTRS if dev else 0) | (BFS_TRUSTED if trusted else 0)
+        if symmetric:
+            flags |= BFS_SYMMETRIC
         h = _vp()
         nnz = int(col.shape[0])
         _check(lib.bfs_graph_create_csr(n, nnz, _ptr(off), ob, _ptr(col) if nnz else None, flags,
                                         ctypes.byref(h)), "bfs_graph_create_csr")
-        return cls(h.value, "csr", n, nnz)
+        g = cls(h.value, "csr", n, nnz)
+        if symmetric is False:
+            g.set_options(claim=1)
+        return g
 
     @classmethod
     def from_dcsc(cls, nrows: int, ncols: int, jc, cp, ir, trusted: bool = False) -> "Graph":
@@ -241,8 +253,9 @@ class Graph:
                                      ctypes.byref(b)), "bfs_graph_info")
         return n.value, nnz.value, b.value
 
-    def set_options(self, mode=0, batch_levels=0, grid_blocks=0, lds_bitmap=0, profile=0):
-        o = Options(mode, batch_levels, grid_blocks, lds_bitmap, profile)
+    def set_options(self, mode=0, batch_levels=0, grid_blocks=0, lds_bitmap=0, profile=0,
+                    claim=0, claim_threshold=0):
+        o = Options(mode, batch_levels, grid_blocks, lds_bitmap, profile, claim, claim_threshold)
         _check(load().bfs_graph_set_options(self.handle, ctypes.byref(o)),
                "bfs_graph_set_options")
 
@@ -265,6 +278,14 @@ class Graph:
         st = RunStats()
         _check(load().bfs_last_stats(self.handle, ctypes.byref(st)), "bfs_last_stats")
         return st
+
+    def level_times(self) -> list:
+        """Per expand launch device ms of the last profiled run."""
+        buf = (ctypes.c_double * 4096)()
+        cnt = _i32()
+        _check(load().bfs_last_level_times(self.handle, buf, 4096, ctypes.byref(cnt)),
+               "bfs_last_level_times")
+        return [buf[i] for i in range(min(cnt.value, 4096))]
 
     def spmspv(self, fidx, fnnz: int, out_idx, out_val, capacity: int, fval=None,
                stream=None) -> int:
@@ -297,8 +318,9 @@ def run_batch(graphs: Sequence[Graph], roots, parents, levels=None, stream=None)
 class Server:
     """Continuous-batching BFS server (bfs_server_*)."""
 
-    def __init__(self, slots: int = 64, memory_budget: int = 0, step_budget_us: int = 0):
-        cfg = ServerConfig(slots, memory_budget, step_budget_us)
+    def __init__(self, slots: int = 64, memory_budget: int = 0, step_budget_us: int = 0,
+                 large_query_nnz: int = 0):
+        cfg = ServerConfig(slots, memory_budget, step_budget_us, large_query_nnz)
         h = _vp()
         _check(load().bfs_server_create(ctypes.byref(cfg), ctypes.byref(h)), "bfs_server_create")
         self.handle = h.value

@@ -49,6 +49,8 @@ void default_options(bfs_options_t* o) {
   o->grid_blocks = 0;
   o->lds_bitmap = 0;
   o->profile = -1;
+  o->claim = 3;
+  o->claim_threshold = 0;
 }
 
 }  // namespace
@@ -120,6 +122,10 @@ int bfs_graph_create_csr(int64_t n, int64_t nnz, const void* row_offsets, int of
       if (e != hipSuccess) rc = hip_fail(e, "upload");
     }
     if (rc == BFS_OK && !(flags & BFS_TRUSTED)) rc = csr_validate(g, s);
+    if (rc == BFS_OK) {
+      if (flags & BFS_SYMMETRIC) c.symmetric = 1;
+      else if (!(flags & BFS_TRUSTED)) rc = csr_check_symmetric(g, s, &c.symmetric);
+    }
     if (rc == BFS_OK) rc = csr_alloc_workspace(g);
     if (rc == BFS_OK) {
       e = hipHostMalloc(&g->h_ctr, sizeof(unsigned long long), hipHostMallocDefault);
@@ -206,8 +212,11 @@ int bfs_graph_info(const bfs_graph_t* g, int64_t* n, int64_t* nnz, int64_t* devi
 
 int bfs_graph_set_options(bfs_graph_t* g, const bfs_options_t* opt) {
   if (!g || !opt) return fail(BFS_ERR_ARG, "NULL argument");
-  if (opt->mode < 0 || opt->mode > 2 || opt->batch_levels < 0 || opt->grid_blocks < 0)
+  if (opt->mode < 0 || opt->mode > 2 || opt->batch_levels < 0 || opt->grid_blocks < 0 ||
+      opt->claim < 0 || opt->claim > 3 || opt->claim_threshold < 0)
     return fail(BFS_ERR_ARG, "option out of range");
+  if (opt->claim) g->opt.claim = opt->claim;
+  if (opt->claim_threshold) g->opt.claim_threshold = opt->claim_threshold;
   if (opt->mode) g->opt.mode = opt->mode;
   if (opt->batch_levels) g->opt.batch_levels = opt->batch_levels;
   if (opt->grid_blocks) g->opt.grid_blocks = opt->grid_blocks;
@@ -227,6 +236,7 @@ int bfs_run_async(bfs_graph_t* g, int32_t root, int32_t* parent, int32_t* level,
   if (!g) return fail(BFS_ERR_ARG, "NULL handle");
   if (g->kind != kCsr) return fail(BFS_ERR_ARG, "bfs_run needs a CSR graph");
   try {
+    std::lock_guard<std::mutex> lk(g->run_mu);
     return csr_run(g, root, parent, level, static_cast<hipStream_t>(hip_stream), false);
   } catch (...) {
     return fail(BFS_ERR_DEVICE, "exception in bfs_run");
@@ -237,6 +247,7 @@ int bfs_run(bfs_graph_t* g, int32_t root, int32_t* parent, int32_t* level) {
   if (!g) return fail(BFS_ERR_ARG, "NULL handle");
   if (g->kind != kCsr) return fail(BFS_ERR_ARG, "bfs_run needs a CSR graph");
   try {
+    std::lock_guard<std::mutex> lk(g->run_mu);
     return csr_run(g, root, parent, level, nullptr, true);
   } catch (...) {
     return fail(BFS_ERR_DEVICE, "exception in bfs_run");
@@ -247,6 +258,20 @@ int bfs_last_stats(bfs_graph_t* g, bfs_run_stats_t* st) {
   if (!g || !st) return fail(BFS_ERR_ARG, "NULL argument");
   if (g->kind != kCsr || !g->stats_valid) return fail(BFS_ERR_ARG, "no completed run");
   return csr_read_stats(g, st);
+}
+
+int bfs_last_level_times(bfs_graph_t* g, double* ms, int32_t capacity, int32_t* count) {
+  if (!g || !count || (capacity > 0 && !ms)) return fail(BFS_ERR_ARG, "NULL argument");
+  if (g->kind != kCsr || !g->stats_valid || !g->profiled)
+    return fail(BFS_ERR_ARG, "no profiled run");
+  BFS_HIP(hipStreamSynchronize(g->last_stream));
+  *count = g->expand_launches;
+  for (int k = 0; k < g->expand_launches && k < capacity; ++k) {
+    float t = 0.f;
+    BFS_HIP(hipEventElapsedTime(&t, g->ev[2 + 2 * k], g->ev[3 + 2 * k]));
+    ms[k] = t;
+  }
+  return BFS_OK;
 }
 
 int bfs_spmspv(bfs_graph_t* block, const bfs_svec_t* frontier, bfs_svec_t* out,

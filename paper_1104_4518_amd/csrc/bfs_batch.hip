@@ -217,6 +217,7 @@ int bfs_tune(bfs_graph_t* g, const char* cache_path) {
                       });
     cand.resize(std::min<size_t>(3, cand.size()));
     if (cand.empty()) cand.push_back(0);
+    std::lock_guard<std::mutex> run_lk(g->run_mu);
     const bfs_options_t saved = g->opt;
     const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     double best = 1e30;

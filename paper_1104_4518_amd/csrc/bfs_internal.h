@@ -40,7 +40,7 @@ enum GraphKind { kCsr = 1, kDcsc = 2 };
 struct LevelState {
   unsigned long long ctr[3];
   int32_t k_expand;   // level the next expand launch processes
-  int32_t k_fold;     // level the next fold launch closes
+  int32_t k_fold;     // level the next finish launch closes
   int32_t depth;      // largest level assigned
   int32_t levels;     // expand launches that found a non-empty frontier
   unsigned long long edges;    // sum of frontier edge totals
@@ -50,6 +50,8 @@ struct LevelState {
   // not expanded, but still marked visited by fold(k)
   unsigned int zcnt[3];
   int32_t error;
+  int32_t mark_levels;   // levels resolved by mark-and-resolve
+  int32_t pad;
 };
 
 struct CsrDev {
@@ -64,6 +66,8 @@ struct CsrDev {
   int64_t* qo[2] = {nullptr, nullptr};   // row start off[v] of each entry
   int64_t* qe[2] = {nullptr, nullptr};   // exclusive edge prefix of each entry
   int32_t* zq = nullptr;         // reached vertices of out-degree 0 (per level)
+  uint8_t* mark = nullptr;       // per-vertex touch marks (nwords * 32 bytes)
+  int symmetric = 0;             // undirected with ascending adjacency (checked or asserted)
   int32_t* jstart = nullptr;     // first queue entry of each expand tile
   int64_t njstart = 0;
   LevelState* state = nullptr;
@@ -112,6 +116,9 @@ struct bfs_graph {
   // cost hints for ordering queries in batches (from earlier runs)
   int32_t hint_depth = 0;
   int64_t hint_edges = 0;
+  // serialises runs that use the handle's own workspace (bfs_run, the
+  // server's whole-GPU lane, bfs_tune)
+  std::mutex run_mu;
 };
 
 namespace bfsi {
@@ -122,6 +129,7 @@ int csr_alloc_workspace(bfs_graph* g);
 int csr_widen(const int32_t* d_src32, int64_t n1, int64_t* d_dst, hipStream_t s);
 void csr_free(bfs_graph* g);
 int csr_validate(bfs_graph* g, hipStream_t s);
+int csr_check_symmetric(bfs_graph* g, hipStream_t s, int* symmetric);
 int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStream_t s,
             bool sync);
 int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st);

@@ -86,8 +86,13 @@ struct bfs_server {
   int device = 0;
   hipStream_t stream = nullptr;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_lane;
   std::thread worker;
+  // whole-GPU lane for queries on large high-degree graphs
+  std::thread lane;
+  hipStream_t lane_stream = nullptr;
+  std::deque<uint64_t> lane_q;
+  int64_t large_nnz = 0;
   bool stop = false;
   int fatal = 0;
   uint64_t next_id = 1;
@@ -106,7 +111,51 @@ struct bfs_server {
   unsigned long long budget_ticks = 0;
 
   void run();
+  void run_lane();
+  bool is_large(const bfs_graph* g) const {
+    return large_nnz > 0 && g->csr.nnz >= large_nnz && g->csr.nnz >= 8 * g->csr.n;
+  }
 };
+
+// Large queries one at a time across the whole GPU (the edge-balanced
+// level kernels), on the lane's own stream, concurrently with the
+// multi-query steps of the main worker.
+void bfs_server::run_lane() {
+  (void)hipSetDevice(device);
+  for (;;) {
+    std::unique_lock<std::mutex> lk(mu);
+    cv_lane.wait(lk, [this] { return stop || !lane_q.empty(); });
+    if (lane_q.empty()) {
+      if (stop) break;
+      continue;
+    }
+    const uint64_t id = lane_q.front();
+    lane_q.pop_front();
+    Ticket& t = tickets[id];
+    t.t_admit = now_s();
+    bfs_graph* g = t.g;
+    const int32_t root = t.root;
+    int32_t* parent = t.parent;
+    int32_t* level = t.level;
+    lk.unlock();
+    bfs_run_stats_t st{};
+    int rc;
+    {
+      std::lock_guard<std::mutex> gl(g->run_mu);
+      rc = bfsi::csr_run(g, root, parent, level, lane_stream, true);
+      if (rc == BFS_OK) rc = bfsi::csr_read_stats(g, &st);
+    }
+    const double t_done = now_s();
+    lk.lock();
+    t.status = rc;
+    t.t_done = t_done;
+    t.depth = st.depth;
+    t.edges = st.edges_traversed;
+    g->users.fetch_sub(1);
+    --in_flight;
+    cv_done.notify_all();
+  }
+}
 
 void bfs_server::run() {
   (void)hipSetDevice(device);
@@ -236,10 +285,13 @@ int bfs_server_create(const bfs_server_config_t* cfg, bfs_server_t** out) {
       if (s->h_qs) (void)hipHostFree(s->h_qs);
       if (s->h_active) (void)hipHostFree(s->h_active);
       if (s->stream) (void)hipStreamDestroy(s->stream);
+      if (s->lane_stream) (void)hipStreamDestroy(s->lane_stream);
       delete s;
       return code;
     };
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->lane_stream, hipStreamNonBlocking);
+    s->large_nnz = cfg->large_query_nnz == 0 ? ((int64_t)1 << 23) : cfg->large_query_nnz;
     const size_t nq = (size_t)cfg->slots;
     if (e == hipSuccess) e = hipMalloc(&s->d_qs, nq * sizeof(MQuery));
     if (e == hipSuccess) e = hipMalloc(&s->d_active, nq * 4);
@@ -269,6 +321,7 @@ int bfs_server_create(const bfs_server_config_t* cfg, bfs_server_t** out) {
     s->budget_ticks = (unsigned long long)rate_khz * (unsigned long long)us / 1000ull;
     if (!s->budget_ticks) s->budget_ticks = 1;
     s->worker = std::thread([s] { s->run(); });
+    s->lane = std::thread([s] { s->run_lane(); });
     *out = s;
     return BFS_OK;
   } catch (...) {
@@ -292,7 +345,8 @@ int bfs_server_submit(bfs_server_t* s, bfs_graph_t* g, int32_t root, int32_t* pa
     (void)hipGetLastError();
     return fail(BFS_ERR_ARG, "server outputs must be device arrays");
   }
-  if (bfsi::multi_ws_bytes(g->csr.n) > s->arena_bytes)
+  const bool large = s->is_large(g);
+  if (!large && bfsi::multi_ws_bytes(g->csr.n) > s->arena_bytes)
     return fail(BFS_ERR_CAPACITY, "query workspace exceeds the server memory budget");
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return fail(BFS_ERR_BUSY, "server is shutting down");
@@ -306,9 +360,14 @@ int bfs_server_submit(bfs_server_t* s, bfs_graph_t* g, int32_t root, int32_t* pa
   t.t_arrive = now_s();
   g->users.fetch_add(1);
   ++s->in_flight;
-  s->waiting.push_back(id);
+  if (large) {
+    s->lane_q.push_back(id);
+    s->cv_lane.notify_one();
+  } else {
+    s->waiting.push_back(id);
+    s->cv_work.notify_one();
+  }
   *ticket = id;
-  s->cv_work.notify_one();
   return BFS_OK;
 }
 
@@ -363,9 +422,13 @@ int bfs_server_destroy(bfs_server_t* s) {
     s->cv_done.wait(lk, [s] { return s->in_flight == 0; });
     s->stop = true;
     s->cv_work.notify_all();
+    s->cv_lane.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
+  if (s->lane.joinable()) s->lane.join();
   (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->lane_stream);
+  (void)hipStreamDestroy(s->lane_stream);
   (void)hipFree(s->d_qs);
   (void)hipFree(s->d_active);
   (void)hipFree(s->d_arena);

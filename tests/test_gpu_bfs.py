@@ -135,19 +135,55 @@ def test_stream_argument():
 
 
 def test_launch_shapes_do_not_change_results():
-    """Schedule perturbation: grid sizes and host-check batching."""
+    """Schedule perturbation: grid sizes, host-check batching and both ways of
+    resolving a level's new vertices (atomicMin claims, mark-and-resolve)."""
     g = graphgen.rmat_csr(15, 16, 31)
     G = graph_on_device(g)
     r = int(graphgen.roots(g, 1, 8)[0])
     op, ol = oracle.bfs_graph(g, r)
-    for grid, batch in [(1, 1), (3, 2), (17, 16), (256, 1), (4096, 5)]:
-        G.set_options(grid_blocks=grid, batch_levels=batch)
-        say(f"grid {grid} batch {batch}")
-        p, lv = gpu_bfs(G, r)
-        assert np.array_equal(p, op) and np.array_equal(lv, ol), (grid, batch)
+    for claim in (1, 2, 3):
+        for grid, batch in [(1, 1), (3, 2), (17, 16), (256, 1), (4096, 5)]:
+            G.set_options(grid_blocks=grid, batch_levels=batch, claim=claim)
+            say(f"claim {claim} grid {grid} batch {batch}")
+            p, lv = gpu_bfs(G, r, want_level=(grid % 2 == 1))
+            assert np.array_equal(p, op), (claim, grid, batch)
+            if lv is not None:
+                assert np.array_equal(lv, ol), (claim, grid, batch)
+            st = G.last_stats()
+            if claim == 1:
+                assert st.mark_levels == 0
+            if claim == 2:
+                assert st.mark_levels == st.levels
     for rep in range(5):
         p, lv = gpu_bfs(G, r)
         assert np.array_equal(p, op) and np.array_equal(lv, ol)
+
+
+def test_symmetry_detection_selects_mark_levels():
+    g = graphgen.rmat_csr(16, 16, 12)
+    r = int(graphgen.roots(g, 1, 3)[0])
+    G = graph_on_device(g)                     # checked at create: symmetric
+    say("symmetric detection")
+    assert_bfs_equal(g, G, r)
+    assert G.last_stats().mark_levels >= 1
+    Gt = B.Graph.from_csr(g.n, g.off, g.col, trusted=True)   # unchecked: claims only
+    assert_bfs_equal(g, Gt, r)
+    assert Gt.last_stats().mark_levels == 0
+    Gs = B.Graph.from_csr(g.n, g.off, g.col, trusted=True, symmetric=True)
+    assert_bfs_equal(g, Gs, r)
+    assert Gs.last_stats().mark_levels >= 1
+    # an asymmetric graph is detected and keeps atomicMin claims
+    rng = np.random.default_rng(1)
+    n = 5000
+    src, dst = rng.integers(0, n, 60000), rng.integers(0, n, 60000)
+    order = np.lexsort((dst, src))
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(np.bincount(src[order], minlength=n))
+    gd = graphgen.CSR(n, off, dst[order].astype(np.int32))
+    Gd = graph_on_device(gd)
+    Gd.set_options(claim=2)
+    assert_bfs_equal(gd, Gd, 7)
+    assert Gd.last_stats().mark_levels == 0
 
 
 def test_profile_stats():
@@ -196,7 +232,7 @@ def test_rmat22_config_sampled_roots():
     checker on 5 more."""
     g = graphgen.config_graph("rmat22")
     roots = graphgen.config_roots("rmat22", g)
-    G = graph_on_device(g, trusted=False)
+    G = B.Graph.from_csr(g.n, g.off, g.col, trusted=True, symmetric=True)   # as benchmarked
     for r in roots[:3]:
         say(f"rmat22 root {r}")
         assert_bfs_equal(g, G, r)
@@ -204,3 +240,7 @@ def test_rmat22_config_sampled_roots():
         say(f"rmat22 checker root {r}")
         p, lv = gpu_bfs(G, r)
         assert oracle.check_bfs(g, int(r), p, lv) == (0, -1)
+    for claim in (1, 2):
+        G.set_options(claim=claim)
+        say(f"rmat22 claim mode {claim}")
+        assert_bfs_equal(g, G, roots[8])

@@ -49,6 +49,13 @@ def test_server_mixed_queries():
     _check_all(S, subs)
     S.drain()
     S.destroy()
+    # the R-MAT graphs above 2^16 adjacencies now take the whole-GPU lane,
+    # concurrently with the grid queries in the multi-query steps
+    S = B.Server(slots=16, large_query_nnz=1 << 16)
+    say(f"server with lane {len(items)} queries")
+    subs = _submit_all(S, items)
+    _check_all(S, subs)
+    S.destroy()
 
 
 def test_server_admission_by_memory_and_resume():

@@ -114,6 +114,8 @@ typedef struct bfs_options {
                            2 = mark-and-resolve whenever the graph is symmetric */
   int32_t claim_threshold; /* frontier edges from which a level uses mark-and-resolve
                               (0 = keep; default max(n / 64, 4096)) */
+  int32_t mark_tile;    /* edges per workgroup tile of mark-and-resolve expands: 2048 or
+                           4096 (0 = keep; default 2048) */
 } bfs_options_t;
 
 /* ---------------------------------------------------------------- graphs */
@@ -173,12 +175,23 @@ int bfs_run_async(bfs_graph_t* g, int32_t root, int32_t* parent, int32_t* level,
 /* Statistics of the last completed run (synchronises the handle's stream). */
 int bfs_last_stats(bfs_graph_t* g, bfs_run_stats_t* st);
 
+/* One level of the last profiled run. */
+typedef struct bfs_level_info {
+  int32_t level;        /* k: the level whose vertices this step discovered */
+  int32_t mark;         /* 1 = mark-and-resolve, 0 = atomicMin claims */
+  int64_t frontier;     /* vertices of frontier k-1 that were expanded */
+  int64_t edges;        /* their adjacencies */
+  double expand_ms;     /* device time of the expand launch */
+  double finish_ms;     /* device time of the finish launch */
+} bfs_level_info_t;
+
 /*
- * Device time of each expand launch of the last run, in launch order (level
- * 1, 2, ...), when options.profile = 1. Writes min(capacity, launches)
- * values to ms and the launch count to *count.
+ * Per-level record of the last run made with options.profile = 1, for the
+ * first min(capacity, 4096) launched levels (empty trailing levels included,
+ * with frontier 0). *count receives the number of launched levels.
  */
-int bfs_last_level_times(bfs_graph_t* g, double* ms, int32_t capacity, int32_t* count);
+int bfs_last_level_info(bfs_graph_t* g, bfs_level_info_t* out, int32_t capacity,
+                        int32_t* count);
 
 /*
  * Local product of one 2D share (Algorithm 3's SpMSV step, section 4.2):

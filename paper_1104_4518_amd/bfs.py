@@ -56,11 +56,17 @@ class RunStats(ctypes.Structure):
                 ("total_ms", ctypes.c_double)]
 
 
+class LevelInfo(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("mark", ctypes.c_int32),
+                ("frontier", ctypes.c_int64), ("edges", ctypes.c_int64),
+                ("expand_ms", ctypes.c_double), ("finish_ms", ctypes.c_double)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch_levels", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("lds_bitmap", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("claim", ctypes.c_int32),
-                ("claim_threshold", ctypes.c_int32)]
+                ("claim_threshold", ctypes.c_int32), ("mark_tile", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -119,8 +125,7 @@ def load(build_if_missing: bool = True):
         "bfs_run": [_vp, _i32, _vp, _vp],
         "bfs_run_async": [_vp, _i32, _vp, _vp, _vp],
         "bfs_last_stats": [_vp, ctypes.POINTER(RunStats)],
-        "bfs_last_level_times": [_vp, ctypes.POINTER(ctypes.c_double), _i32,
-                                 ctypes.POINTER(_i32)],
+        "bfs_last_level_info": [_vp, ctypes.POINTER(LevelInfo), _i32, ctypes.POINTER(_i32)],
         "bfs_spmspv": [_vp, ctypes.POINTER(SVec), ctypes.POINTER(SVec), _vp],
         "bfs_run_batch": [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_i32), ctypes.POINTER(_vp),
                           ctypes.POINTER(_vp), _vp],
@@ -254,8 +259,9 @@ class Graph:
         return n.value, nnz.value, b.value
 
     def set_options(self, mode=0, batch_levels=0, grid_blocks=0, lds_bitmap=0, profile=0,
-                    claim=0, claim_threshold=0):
-        o = Options(mode, batch_levels, grid_blocks, lds_bitmap, profile, claim, claim_threshold)
+                    claim=0, claim_threshold=0, mark_tile=0):
+        o = Options(mode, batch_levels, grid_blocks, lds_bitmap, profile, claim, claim_threshold,
+                    mark_tile)
         _check(load().bfs_graph_set_options(self.handle, ctypes.byref(o)),
                "bfs_graph_set_options")
 
@@ -279,13 +285,14 @@ class Graph:
         _check(load().bfs_last_stats(self.handle, ctypes.byref(st)), "bfs_last_stats")
         return st
 
-    def level_times(self) -> list:
-        """Per expand launch device ms of the last profiled run."""
-        buf = (ctypes.c_double * 4096)()
+    def level_info(self) -> list:
+        """Per-level records of the last profiled run (dicts)."""
+        buf = (LevelInfo * 4096)()
         cnt = _i32()
-        _check(load().bfs_last_level_times(self.handle, buf, 4096, ctypes.byref(cnt)),
-               "bfs_last_level_times")
-        return [buf[i] for i in range(min(cnt.value, 4096))]
+        _check(load().bfs_last_level_info(self.handle, buf, 4096, ctypes.byref(cnt)),
+               "bfs_last_level_info")
+        return [{f: getattr(buf[i], f) for f, _ in LevelInfo._fields_}
+                for i in range(min(cnt.value, 4095))]
 
     def spmspv(self, fidx, fnnz: int, out_idx, out_val, capacity: int, fval=None,
                stream=None) -> int:

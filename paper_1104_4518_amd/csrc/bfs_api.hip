@@ -51,6 +51,7 @@ void default_options(bfs_options_t* o) {
   o->profile = -1;
   o->claim = 3;
   o->claim_threshold = 0;
+  o->mark_tile = 2048;
 }
 
 }  // namespace
@@ -215,6 +216,9 @@ int bfs_graph_set_options(bfs_graph_t* g, const bfs_options_t* opt) {
   if (opt->mode < 0 || opt->mode > 2 || opt->batch_levels < 0 || opt->grid_blocks < 0 ||
       opt->claim < 0 || opt->claim > 3 || opt->claim_threshold < 0)
     return fail(BFS_ERR_ARG, "option out of range");
+  if (opt->mark_tile && opt->mark_tile != 2048 && opt->mark_tile != 4096)
+    return fail(BFS_ERR_ARG, "mark_tile must be 2048 or 4096");
+  if (opt->mark_tile) g->opt.mark_tile = opt->mark_tile;
   if (opt->claim) g->opt.claim = opt->claim;
   if (opt->claim_threshold) g->opt.claim_threshold = opt->claim_threshold;
   if (opt->mode) g->opt.mode = opt->mode;
@@ -260,18 +264,12 @@ int bfs_last_stats(bfs_graph_t* g, bfs_run_stats_t* st) {
   return csr_read_stats(g, st);
 }
 
-int bfs_last_level_times(bfs_graph_t* g, double* ms, int32_t capacity, int32_t* count) {
-  if (!g || !count || (capacity > 0 && !ms)) return fail(BFS_ERR_ARG, "NULL argument");
+int bfs_last_level_info(bfs_graph_t* g, bfs_level_info_t* out, int32_t capacity,
+                        int32_t* count) {
+  if (!g || !count || (capacity > 0 && !out)) return fail(BFS_ERR_ARG, "NULL argument");
   if (g->kind != kCsr || !g->stats_valid || !g->profiled)
     return fail(BFS_ERR_ARG, "no profiled run");
-  BFS_HIP(hipStreamSynchronize(g->last_stream));
-  *count = g->expand_launches;
-  for (int k = 0; k < g->expand_launches && k < capacity; ++k) {
-    float t = 0.f;
-    BFS_HIP(hipEventElapsedTime(&t, g->ev[2 + 2 * k], g->ev[3 + 2 * k]));
-    ms[k] = t;
-  }
-  return BFS_OK;
+  return csr_level_info(g, out, capacity, count);
 }
 
 int bfs_spmspv(bfs_graph_t* block, const bfs_svec_t* frontier, bfs_svec_t* out,

@@ -27,7 +27,7 @@
 //              the first neighbour one level up in its ascending adjacency
 //              list (for an undirected graph that is the minimum frontier
 //              id adjacent to it), appends it to the next frontier, sets
-//              the visited word and clears the marks.
+//              the visited word and turns the marks into the level's tag.
 //
 // Both ways give the same parents: the unique minimum-id neighbour one
 // level up. Appends to the next frontier are aggregated per workgroup into
@@ -36,19 +36,31 @@
 #include "bfs_internal.h"
 
 #include <algorithm>
+#include <cstddef>
+#include <vector>
 
 namespace bfsi {
 namespace {
 
 // jstart granularity and claim-path tile: 1024 edges (256 threads x 4)
 constexpr int kTileJ = 1024;
-// mark path: super-tiles of 4 x 1024 edges, 16 edges per thread
-constexpr int kMarkSub = 4;
-constexpr int kMarkItems = 16;
-// LDS of the expand kernel: the larger of the two paths' needs
-constexpr int kLdsQe = kTileJ * kMarkSub + 1;   // staged row starts (int64)
-constexpr int kLdsBytes = kLdsQe * 8;
-static_assert((kTileJ + 1) * 8 + kTileJ * (4 + 4 + 8) <= kLdsBytes, "claim path LDS");
+// mark path: super-tiles of MSUB x 1024 edges (MSUB = 2 or 4, a launch
+// shape choice), MSUB * 4 edges per thread
+constexpr int kMarkSubMax = 4;
+// mark-and-resolve: vertices of degree above this search their parent with
+// the whole wave instead of one thread
+constexpr int kSerialScan = 64;
+// LDS of the expand kernel: the larger of the two paths' needs (staged
+// row starts of a mark super-tile, or the claim path's rows and owners)
+template <int MSUB>
+constexpr int lds_bytes() { return (kTileJ * MSUB + 1) * 8; }
+static_assert((kTileJ + 1) * 8 + kTileJ * (4 + 4) <= lds_bytes<2>(), "claim path LDS");
+
+// Mark bytes: 0 = not reached, 1 = touched by the current level's frontier,
+// 2 + (level mod 3) = reached at that level. A neighbour of a vertex at level
+// k lies at level k-1, k or k+1 (or is unreached), so the tag identifies
+// "one level up" exactly.
+__device__ __forceinline__ uint8_t level_tag(int k) { return (uint8_t)(2 + k % 3); }
 
 struct Queues {
   int32_t* qv[2];
@@ -56,9 +68,20 @@ struct Queues {
   int64_t* qe[2];
 };
 
-__device__ __forceinline__ bool mark_level(unsigned long long cin, int cbits, int symmetric,
-                                           long long thresh) {
-  return symmetric && (long long)(cin >> cbits) >= thresh;
+// Level selection: mark-and-resolve when the graph is symmetric and the
+// input frontier is large in both edges and vertices (a small frontier makes
+// every new vertex search far for one of its few frontier neighbours).
+struct MarkPolicy {
+  int symmetric;
+  long long min_edges;
+  long long min_vertices;
+};
+
+__device__ __forceinline__ bool mark_level(unsigned long long cin, int cbits,
+                                           const MarkPolicy& mp) {
+  const unsigned long long cmask = (1ull << cbits) - 1;
+  return mp.symmetric && (long long)(cin >> cbits) >= mp.min_edges &&
+         (long long)(cin & cmask) >= mp.min_vertices;
 }
 
 __global__ void k_init(int64_t n, int32_t* __restrict__ parent, int32_t* __restrict__ level,
@@ -79,12 +102,13 @@ __global__ void k_init(int64_t n, int32_t* __restrict__ parent, int32_t* __restr
 }
 
 __global__ void k_seed(const int64_t* __restrict__ off, int32_t root, int32_t* parent,
-                       int32_t* level, uint32_t* vis, Queues q, int32_t* jstart, LevelState* st,
-                       int cbits) {
+                       int32_t* level, uint32_t* vis, uint8_t* mark, Queues q, int32_t* jstart,
+                       LevelState* st, int cbits) {
   // jstart holds two maps (frontier parity 0 and 1); frontier 0 uses the first
   parent[root] = root;
   if (level) level[root] = 0;
   vis[root >> 5] |= 1u << (root & 31);
+  if (mark) mark[root] = level_tag(0);
   const int64_t o = off[root];
   const int64_t d = off[root + 1] - o;
   q.qv[0][0] = root;
@@ -145,14 +169,14 @@ __device__ __forceinline__ void map_tiles(int32_t* __restrict__ jstart, long lon
   for (long long w = (e + kTileJ - 1) / kTileJ; w * kTileJ < e + d; ++w) jstart[w] = j;
 }
 
-template <int BLOCK>
+template <int BLOCK, int MSUB>
 __global__ __launch_bounds__(BLOCK) void k_expand(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const uint32_t* __restrict__ vis, int32_t* __restrict__ parent, int32_t* __restrict__ level,
     uint8_t* __restrict__ mark, Queues q, int32_t* __restrict__ jstart_base, int64_t njs,
-    int32_t* __restrict__ zq, LevelState* st, int cbits, int symmetric, long long thresh) {
+    int32_t* __restrict__ zq, LevelState* st, int cbits, MarkPolicy mp) {
   constexpr int WAVES = BLOCK / 64;
-  __shared__ __align__(16) unsigned char s_raw[kLdsBytes];
+  __shared__ __align__(16) unsigned char s_raw[lds_bytes<MSUB>()];
   __shared__ long long s_wc[WAVES], s_wd[WAVES];
   __shared__ unsigned long long s_base;
   __shared__ int s_cnt;
@@ -172,7 +196,11 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
       st->levels = k;
       st->edges += (unsigned long long)T;
       st->frontier_total += (unsigned long long)F;
-      if (mark_level(cin, cbits, symmetric, thresh)) st->mark_levels += 1;
+      if (mark_level(cin, cbits, mp)) st->mark_levels += 1;
+    }
+    if (k < kLevelHist) {
+      st->hist[k] = cin;
+      st->hist_mark[k] = mark_level(cin, cbits, mp) ? 1 : 0;
     }
   }
   if (F == 0) return;
@@ -185,16 +213,16 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   const int64_t* __restrict__ qe_in = q.qe[kin & 1];
   const int tid = threadIdx.x;
 
-  if (mark_level(cin, cbits, symmetric, thresh)) {
+  if (mark_level(cin, cbits, mp)) {
     // ---------------------------------------------------------- mark path
-    constexpr int TILE = kTileJ * kMarkSub;
-    static_assert(BLOCK * kMarkItems == TILE, "mark tile shape");
+    constexpr int TILE = kTileJ * MSUB;
+    constexpr int kMarkItems = TILE / BLOCK;
     const int64_t nitems = (T + TILE - 1) / TILE;
     for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
       const int64_t e0 = w * TILE;
       const int64_t e1 = min(e0 + (int64_t)TILE, T);
-      const int32_t j0 = jstart[w * kMarkSub];
-      const int32_t j1 = ((w + 1) * kMarkSub < njt) ? jstart[(w + 1) * kMarkSub] : (int32_t)(F - 1);
+      const int32_t j0 = jstart[w * MSUB];
+      const int32_t j1 = ((w + 1) * MSUB < njt) ? jstart[(w + 1) * MSUB] : (int32_t)(F - 1);
       const int R = j1 - j0 + 1;
       for (int r = tid; r < R; r += BLOCK) s_qe[r] = qe_in[j0 + r];
       __syncthreads();
@@ -233,7 +261,6 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   constexpr int ITEMS = kTileJ / BLOCK;
   int32_t* s_ov = reinterpret_cast<int32_t*>(s_raw + (kTileJ + 1) * 8);
   int32_t* s_od = s_ov + kTileJ;
-  long long* s_oo = reinterpret_cast<long long*>(s_od + kTileJ);
   int32_t* __restrict__ qv_out = q.qv[k & 1];
   int64_t* __restrict__ qo_out = q.qo[k & 1];
   int64_t* __restrict__ qe_out = q.qe[k & 1];
@@ -274,12 +301,11 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
           }
         }
       }
-      int64_t vo = 0;
       int32_t deg = 0;
       if (own) {
         if (level) level[v] = k;
-        vo = off[v];
-        deg = (int32_t)(off[v + 1] - vo);
+        if (mp.symmetric) mark[v] = level_tag(k);
+        deg = (int32_t)(off[v + 1] - off[v]);
         ++my_reached;
       }
       const bool enq = own && deg > 0;
@@ -292,7 +318,6 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
           const int p = base + lanes_below(m);
           s_ov[p] = v;
           s_od[p] = deg;
-          s_oo[p] = vo;
         }
       }
       // reached but nothing to expand (out-degree 0): finish(k) marks it visited
@@ -333,7 +358,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
         if (p < C) {
           const int64_t slot = bc + p;
           qv_out[slot] = s_ov[p];
-          qo_out[slot] = s_oo[p];
+          qo_out[slot] = off[s_ov[p]];   // read moments ago by the owner: a cache hit
           qe_out[slot] = run;
           map_tiles(jstart_out, run, s_od[p], (int32_t)slot);
           run += s_od[p];
@@ -365,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, uint32_t* __restrict__ vis,
     int32_t* __restrict__ parent, int32_t* __restrict__ level, uint8_t* __restrict__ mark,
     Queues q, int32_t* __restrict__ jstart_base, int64_t njs, const int32_t* __restrict__ zq,
-    LevelState* st, int cbits, int64_t nwords, int symmetric, long long thresh) {
+    LevelState* st, int cbits, int64_t nwords, MarkPolicy mp) {
   __shared__ long long s_wc[BLOCK / 64], s_wd[BLOCK / 64];
   __shared__ unsigned long long s_base;
   const int k = st->k_fold;
@@ -376,7 +401,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int tid = threadIdx.x;
 
-  if (!mark_level(cin, cbits, symmetric, thresh)) {
+  if (!mark_level(cin, cbits, mp)) {
     // claim level: visited bits of the new frontier and of its out-degree-0
     // vertices
     const unsigned long long c = st->ctr[k % 3];
@@ -400,22 +425,28 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   int64_t* __restrict__ qo_out = q.qo[k & 1];
   int64_t* __restrict__ qe_out = q.qe[k & 1];
   unsigned long long* ctr_out = &st->ctr[k % 3];
-  const uint4* __restrict__ mark4 = reinterpret_cast<const uint4*>(mark);
-  const int32_t kprev = k - 1;
+  uint4* __restrict__ mark4 = reinterpret_cast<uint4*>(mark);
+  const uint8_t tprev = level_tag(k - 1);
+  const uint32_t tcur = level_tag(k);
   unsigned int my_reached = 0;
   for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nwords; base += stride) {
     const int64_t w = base + tid;
     uint32_t m = 0;
+    uint32_t x[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     if (w < nwords) {
       const uint4 a = mark4[2 * w], b = mark4[2 * w + 1];
-      const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+      x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int byte = 0; byte < 4; ++byte)
-          if ((x[i] >> (8 * byte)) & 0xFFu) m |= 1u << (4 * i + byte);
+          if (((x[i] >> (8 * byte)) & 0xFFu) == 1u) m |= 1u << (4 * i + byte);
     }
     long long cnt = __popc(m), dsum = 0;
+    // marked vertices whose parent was not among their first kSerialScan
+    // adjacencies: the wave finishes their search together
+    uint32_t long_bits = 0;
     for (uint32_t bits = m; bits; bits &= bits - 1) {
       const int64_t v = (w << 5) + (__ffs(bits) - 1);
       dsum += off[v + 1] - off[v];
@@ -435,20 +466,31 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
     int64_t slot = (int64_t)(b0 & cmask) + ex_c;
     long long epos = (long long)(b0 >> cbits) + ex_d;
     for (uint32_t bits = m; bits; bits &= bits - 1) {
-      const int32_t v = (int32_t)((w << 5) + (__ffs(bits) - 1));
+      const int b = __ffs(bits) - 1;
+      const int32_t v = (int32_t)((w << 5) + b);
       const int64_t o = off[v];
       const int64_t d = off[v + 1] - o;
-      // parent: first neighbour one level up in the ascending adjacency
+      // parent: first neighbour one level up in the ascending adjacency,
+      // four adjacencies per step over the first kSerialScan of them
       int32_t p = -1;
-      for (int64_t e = o; e < o + d; ++e) {
-        const int32_t u = col[e];
-        if (level[u] == kprev) {
-          p = u;
-          break;
-        }
+      const int64_t lim = o + min(d, (int64_t)kSerialScan);
+      for (int64_t e = o; e < lim && p < 0; e += 4) {
+        int32_t u[4];
+        uint8_t t[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) u[i] = e + i < lim ? col[e + i] : 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t[i] = e + i < lim ? mark[u[i]] : (uint8_t)0;
+#pragma unroll
+        for (int i = 3; i >= 0; --i)
+          if (t[i] == tprev) p = u[i];
       }
-      parent[v] = p;
-      level[v] = k;
+      if (p >= 0 || d <= kSerialScan) {
+        parent[v] = p;
+        if (level) level[v] = k;
+      } else {
+        long_bits |= 1u << b;
+      }
       qv_out[slot] = v;
       qo_out[slot] = o;
       qe_out[slot] = epos;
@@ -456,10 +498,49 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
       ++slot;
       epos += d;
     }
+    // vertices not resolved by their first kSerialScan adjacencies: the wave
+    // scans the rest 64 adjacencies per step and takes the first
+    // (smallest-id) neighbour one level up
+    const int lane = lane_id();
+    for (;;) {
+      const unsigned long long pend = wave_ballot(long_bits != 0u);
+      if (!pend) break;
+      const int leader = __ffsll((long long)pend) - 1;
+      const int lb = long_bits ? __ffs(long_bits) - 1 : 0;
+      const int32_t v = __shfl((int32_t)((w << 5) + lb), leader, 64);
+      const int64_t o = off[v] + kSerialScan;
+      const int64_t end = off[v + 1];
+      int32_t p = -1;
+      for (int64_t base = o; base < end; base += 64) {
+        const int64_t e = base + lane;
+        int32_t u = 0;
+        bool hit = false;
+        if (e < end) {
+          u = col[e];
+          hit = mark[u] == tprev;
+        }
+        const unsigned long long hb = wave_ballot(hit);
+        if (hb) {
+          p = __shfl(u, __ffsll((long long)hb) - 1, 64);
+          break;
+        }
+      }
+      if (lane == leader) {
+        parent[v] = p;
+        if (level) level[v] = k;
+        long_bits &= long_bits - 1;
+      }
+    }
     if (m) {
-      uint4* mw = reinterpret_cast<uint4*>(mark);
-      mw[2 * w] = make_uint4(0u, 0u, 0u, 0u);
-      mw[2 * w + 1] = make_uint4(0u, 0u, 0u, 0u);
+      // touched bytes become this level's tag
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int byte = 0; byte < 4; ++byte)
+          if ((m >> (4 * i + byte)) & 1u)
+            x[i] = (x[i] & ~(0xFFu << (8 * byte))) | (tcur << (8 * byte));
+      mark4[2 * w] = make_uint4(x[0], x[1], x[2], x[3]);
+      mark4[2 * w + 1] = make_uint4(x[4], x[5], x[6], x[7]);
       vis[w] |= m;
       my_reached += __popc(m);
     }
@@ -563,7 +644,7 @@ constexpr int kFinishBlock = 256;
 int csr_alloc_workspace(bfs_graph* g) {
   CsrDev& c = g->csr;
   c.nwords = (c.n + 31) / 32;
-  c.njstart = c.nnz / kTileJ + 2 + kMarkSub;
+  c.njstart = c.nnz / kTileJ + 2 + kMarkSubMax;
   BFS_HIP(hipMalloc(&c.vis, (size_t)std::max<int64_t>(c.nwords, 1) * 4));
   for (int b = 0; b < 2; ++b) {
     BFS_HIP(hipMalloc(&c.qv[b], (size_t)c.n * 4));
@@ -654,10 +735,12 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
 
   // claim policy of this run
   const int claim = g->opt.claim > 0 ? g->opt.claim : 3;
-  const int use_mark = (claim != 1) && c.symmetric;
-  long long thresh = g->opt.claim_threshold > 0 ? (long long)g->opt.claim_threshold
-                                                : std::max<long long>(c.n / 64, 4096);
-  if (claim == 2) thresh = 1;
+  MarkPolicy mp;
+  mp.symmetric = (claim != 1) && c.symmetric;
+  mp.min_edges = g->opt.claim_threshold > 0 ? (long long)g->opt.claim_threshold
+                                            : std::max<long long>(c.n / 64, 4096);
+  mp.min_vertices = std::max<long long>(c.n / 1024, 1024);
+  if (claim == 2) mp.min_edges = mp.min_vertices = 1;
 
   int32_t* d_parent = parent;
   int32_t* d_level = level;
@@ -667,9 +750,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     if (!c.tmp_parent) BFS_HIP(hipMalloc(&c.tmp_parent, (size_t)c.n * 4));
     d_parent = c.tmp_parent;
   }
-  // the mark path reads levels, so it needs a level array even when the
-  // caller does not ask for one
-  if (host_level || (!level && use_mark)) {
+  if (host_level) {
     if (!c.tmp_level) BFS_HIP(hipMalloc(&c.tmp_level, (size_t)c.n * 4));
     d_level = c.tmp_level;
   }
@@ -692,14 +773,17 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   }
   k_init<<<std::max(igrid, 1), ib, 0, s>>>(c.n, d_parent, d_level, c.vis, c.nwords,
                                            reinterpret_cast<uint4*>(c.mark));
-  k_seed<<<1, 1, 0, s>>>(c.off, root, d_parent, d_level, c.vis, q, c.jstart, c.state, c.cbits);
+  k_seed<<<1, 1, 0, s>>>(c.off, root, d_parent, d_level, c.vis, mp.symmetric ? c.mark : nullptr,
+                         q, c.jstart, c.state, c.cbits);
 
-  static int ge_cache = 0, gf_cache = 0;
-  if (!ge_cache) {
-    ge_cache = grid_for(g->device, (const void*)k_expand<kExpandBlock>, kExpandBlock, 4);
-    gf_cache = grid_for(g->device, (const void*)k_finish<kFinishBlock>, kFinishBlock, 4);
-  }
-  const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache;
+  // expand launch shape: mark super-tile of 2048 or 4096 edges
+  const bool wide = g->opt.mark_tile == 4096;
+  const void* kexp = wide ? (const void*)k_expand<kExpandBlock, 4>
+                          : (const void*)k_expand<kExpandBlock, 2>;
+  static int ge_cache[2] = {0, 0}, gf_cache = 0;
+  if (!ge_cache[wide]) ge_cache[wide] = grid_for(g->device, kexp, kExpandBlock, 8);
+  if (!gf_cache) gf_cache = grid_for(g->device, (const void*)k_finish<kFinishBlock>, kFinishBlock, 4);
+  const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache[wide];
   const int gf = gf_cache;
   BFS_HIP(hipGetLastError());
 
@@ -711,22 +795,27 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   for (;;) {
     for (int b = 0; b < batch; ++b) {
       if (prof) {
-        const size_t need = 2 * (size_t)(k + 1) + 2;
+        const size_t need = 3 * (size_t)(k + 1) + 2;
         while (g->ev.size() < need) {
           hipEvent_t ev;
           BFS_HIP(hipEventCreate(&ev));
           g->ev.push_back(ev);
         }
-        BFS_HIP(hipEventRecord(g->ev[2 + 2 * k], s));
+        BFS_HIP(hipEventRecord(g->ev[2 + 3 * k], s));
       }
-      k_expand<kExpandBlock><<<ge, kExpandBlock, 0, s>>>(c.off, c.col, c.vis, d_parent, d_level,
-                                                         c.mark, q, c.jstart, c.njstart, c.zq,
-                                                         c.state, c.cbits, use_mark, thresh);
-      if (prof) BFS_HIP(hipEventRecord(g->ev[3 + 2 * k], s));
+      if (wide)
+        k_expand<kExpandBlock, 4><<<ge, kExpandBlock, 0, s>>>(
+            c.off, c.col, c.vis, d_parent, d_level, c.mark, q, c.jstart, c.njstart, c.zq,
+            c.state, c.cbits, mp);
+      else
+        k_expand<kExpandBlock, 2><<<ge, kExpandBlock, 0, s>>>(
+            c.off, c.col, c.vis, d_parent, d_level, c.mark, q, c.jstart, c.njstart, c.zq,
+            c.state, c.cbits, mp);
+      if (prof) BFS_HIP(hipEventRecord(g->ev[3 + 3 * k], s));
       k_finish<kFinishBlock><<<gf, kFinishBlock, 0, s>>>(c.off, c.col, c.vis, d_parent, d_level,
                                                          c.mark, q, c.jstart, c.njstart, c.zq,
-                                                         c.state, c.cbits, c.nwords, use_mark,
-                                                         thresh);
+                                                         c.state, c.cbits, c.nwords, mp);
+      if (prof) BFS_HIP(hipEventRecord(g->ev[4 + 3 * k], s));
       ++k;
     }
     BFS_HIP(hipGetLastError());
@@ -751,7 +840,8 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
 int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st) {
   LevelState h;
   BFS_HIP(hipStreamSynchronize(g->last_stream));
-  BFS_HIP(hipMemcpy(&h, g->csr.state, sizeof(h), hipMemcpyDeviceToHost));
+  // the counters only, not the per-level history
+  BFS_HIP(hipMemcpy(&h, g->csr.state, offsetof(LevelState, hist), hipMemcpyDeviceToHost));
   *st = bfs_run_stats_t{};
   st->depth = h.depth;
   st->levels = h.levels;
@@ -764,7 +854,7 @@ int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st) {
     double sum = 0.0;
     for (int k = 0; k < g->expand_launches; ++k) {
       float ms = 0.f;
-      BFS_HIP(hipEventElapsedTime(&ms, g->ev[2 + 2 * k], g->ev[3 + 2 * k]));
+      BFS_HIP(hipEventElapsedTime(&ms, g->ev[2 + 3 * k], g->ev[3 + 3 * k]));
       sum += ms;
     }
     float tot = 0.f;
@@ -772,6 +862,32 @@ int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st) {
     st->expand_ms = sum;
     st->total_ms = tot;
   }
+  return BFS_OK;
+}
+
+int csr_level_info(bfs_graph* g, bfs_level_info_t* out, int32_t capacity, int32_t* count) {
+  BFS_HIP(hipStreamSynchronize(g->last_stream));
+  const int n = std::min<int>(std::min(capacity, g->expand_launches), kLevelHist - 1);
+  std::vector<unsigned long long> hist((size_t)n + 1);
+  std::vector<int32_t> hmark((size_t)n + 1);
+  BFS_HIP(hipMemcpy(hist.data(), g->csr.state->hist, hist.size() * 8, hipMemcpyDeviceToHost));
+  BFS_HIP(hipMemcpy(hmark.data(), g->csr.state->hist_mark, hmark.size() * 4,
+                    hipMemcpyDeviceToHost));
+  const unsigned long long cmask = (1ull << g->csr.cbits) - 1;
+  for (int i = 0; i < n; ++i) {
+    const int k = i + 1;
+    bfs_level_info_t& L = out[i];
+    L.level = k;
+    L.mark = hmark[(size_t)k];
+    L.frontier = (int64_t)(hist[(size_t)k] & cmask);
+    L.edges = (int64_t)(hist[(size_t)k] >> g->csr.cbits);
+    float a = 0.f, b = 0.f;
+    BFS_HIP(hipEventElapsedTime(&a, g->ev[2 + 3 * i], g->ev[3 + 3 * i]));
+    BFS_HIP(hipEventElapsedTime(&b, g->ev[3 + 3 * i], g->ev[4 + 3 * i]));
+    L.expand_ms = a;
+    L.finish_ms = b;
+  }
+  *count = g->expand_launches;
   return BFS_OK;
 }
 

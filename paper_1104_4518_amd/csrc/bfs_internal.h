@@ -52,7 +52,11 @@ struct LevelState {
   int32_t error;
   int32_t mark_levels;   // levels resolved by mark-and-resolve
   int32_t pad;
+  // input frontier counter of each level (profiling; levels < kLevelHist)
+  unsigned long long hist[4096];
+  int32_t hist_mark[4096];
 };
+constexpr int kLevelHist = 4096;
 
 struct CsrDev {
   int64_t n = 0, nnz = 0;
@@ -133,6 +137,7 @@ int csr_check_symmetric(bfs_graph* g, hipStream_t s, int* symmetric);
 int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStream_t s,
             bool sync);
 int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st);
+int csr_level_info(bfs_graph* g, bfs_level_info_t* out, int32_t capacity, int32_t* count);
 
 // bfs_dcsc.hip
 int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate);

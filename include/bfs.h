@@ -72,6 +72,10 @@ typedef enum bfs_status {
 #define BFS_SYMMETRIC 0x4u    /* CSR: caller asserts an undirected graph (every edge in both
                                  rows) with ascending adjacency lists; without this flag and
                                  without BFS_TRUSTED the library checks it at create */
+#define BFS_NO_RELABEL 0x8u   /* CSR: do not build the degree-ordered copy that graphs with
+                                 n >= 2^20 otherwise get for the single-query level kernels
+                                 (results are identical either way; the copy costs nnz * 4 +
+                                 n * 16 device bytes) */
 
 /*
  * Sparse vector with device storage, indices strictly ascending (the 2D

@@ -33,6 +33,7 @@ BFS_ERR_UNSUPPORTED = -8
 BFS_DEVICE_PTRS = 0x1
 BFS_TRUSTED = 0x2
 BFS_SYMMETRIC = 0x4
+BFS_NO_RELABEL = 0x8
 
 _NAMES = {v: k for k, v in globals().items() if k.startswith("BFS_ERR_") or k == "BFS_OK"}
 
@@ -196,9 +197,10 @@ class Graph:
     # ---------------------------------------------------------------- create
     @classmethod
     def from_csr(cls, n: int, off, col, trusted: bool = False,
-                 symmetric: Optional[bool] = None) -> "Graph":
+                 symmetric: Optional[bool] = None, relabel: bool = True) -> "Graph":
         """symmetric=True asserts an undirected graph with ascending rows;
-        None lets the library check it (unless trusted)."""
+        None lets the library check it (unless trusted). relabel=False
+        skips the degree-ordered copy of large graphs."""
         lib = load()
         dev = _is_device(off)
         if dev != _is_device(col):
@@ -212,6 +214,8 @@ class Graph:
         flags = (BFS_DEVICE_PTRS if dev else 0) | (BFS_TRUSTED if trusted else 0)
         if symmetric:
             flags |= BFS_SYMMETRIC
+        if not relabel:
+            flags |= BFS_NO_RELABEL
         h = _vp()
         nnz = int(col.shape[0])
         _check(lib.bfs_graph_create_csr(n, nnz, _ptr(off), ob, _ptr(col) if nnz else None, flags,

@@ -127,6 +127,20 @@ int bfs_graph_create_csr(int64_t n, int64_t nnz, const void* row_offsets, int of
       if (flags & BFS_SYMMETRIC) c.symmetric = 1;
       else if (!(flags & BFS_TRUSTED)) rc = csr_check_symmetric(g, s, &c.symmetric);
     }
+    // degree-ordered copy for the level kernels (large graphs)
+    if (rc == BFS_OK && !(flags & BFS_NO_RELABEL) && n >= ((int64_t)1 << 20) && nnz > 0) {
+      std::vector<int64_t> hoff;
+      const int64_t* ho = nullptr;
+      if (offset_bytes == 8 && !dev) {
+        ho = static_cast<const int64_t*>(row_offsets);
+      } else {
+        hoff.resize((size_t)(n + 1));
+        e = hipMemcpy(hoff.data(), c.off, hoff.size() * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = hip_fail(e, "offsets readback");
+        ho = hoff.data();
+      }
+      if (rc == BFS_OK) rc = csr_relabel(g, ho, s);
+    }
     if (rc == BFS_OK) rc = csr_alloc_workspace(g);
     if (rc == BFS_OK) {
       e = hipHostMalloc(&g->h_ctr, sizeof(unsigned long long), hipHostMallocDefault);

@@ -103,15 +103,18 @@ __global__ void k_init(int64_t n, int32_t* __restrict__ parent, int32_t* __restr
 
 __global__ void k_seed(const int64_t* __restrict__ off, int32_t root, int32_t* parent,
                        int32_t* level, uint32_t* vis, uint8_t* mark, Queues q, int32_t* jstart,
-                       LevelState* st, int cbits) {
-  // jstart holds two maps (frontier parity 0 and 1); frontier 0 uses the first
+                       LevelState* st, int cbits, const int32_t* __restrict__ rank) {
+  // outputs are indexed by the caller's ids; everything else by the ids of
+  // the CSR the level kernels read (degree order when relabelled)
   parent[root] = root;
   if (level) level[root] = 0;
-  vis[root >> 5] |= 1u << (root & 31);
-  if (mark) mark[root] = level_tag(0);
-  const int64_t o = off[root];
-  const int64_t d = off[root + 1] - o;
-  q.qv[0][0] = root;
+  const int32_t r = rank ? rank[root] : root;
+  vis[r >> 5] |= 1u << (r & 31);
+  if (mark) mark[r] = level_tag(0);
+  const int64_t o = off[r];
+  const int64_t d = off[r + 1] - o;
+  // jstart holds two maps (frontier parity 0 and 1); frontier 0 uses the first
+  q.qv[0][0] = r;
   q.qo[0][0] = o;
   q.qe[0][0] = 0;
   for (int64_t w = 0; w * kTileJ < d; ++w) jstart[w] = 0;
@@ -174,7 +177,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const uint32_t* __restrict__ vis, int32_t* __restrict__ parent, int32_t* __restrict__ level,
     uint8_t* __restrict__ mark, Queues q, int32_t* __restrict__ jstart_base, int64_t njs,
-    int32_t* __restrict__ zq, LevelState* st, int cbits, MarkPolicy mp) {
+    int32_t* __restrict__ zq, LevelState* st, int cbits, MarkPolicy mp,
+    const int32_t* __restrict__ inv) {
   constexpr int WAVES = BLOCK / 64;
   __shared__ __align__(16) unsigned char s_raw[lds_bytes<MSUB>()];
   __shared__ long long s_wc[WAVES], s_wd[WAVES];
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     for (int i = 0; i < ITEMS; ++i) {
       const int64_t e = e0 + (int64_t)i * BLOCK + tid;
       bool own = false;
-      int32_t v = 0;
+      int32_t v = 0, vout = 0;
       if (e < e1) {
         // row of edge e: last r with s_qe[r] <= e (rows are non-empty)
         int lo = 0, hi = R - 1;
@@ -291,19 +295,21 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
           if (s_qe[mid] <= e) lo = mid; else hi = mid - 1;
         }
         const int64_t j = j0 + lo;
-        const uint32_t u = (uint32_t)qv_in[j];
+        const int32_t uj = qv_in[j];
+        const uint32_t u = (uint32_t)(inv ? inv[uj] : uj);   // caller's id of the frontier vertex
         v = col[qo_in[j] + (e - s_qe[lo])];
         if (!((vis[v >> 5] >> (v & 31)) & 1u)) {
-          const uint32_t cur = reinterpret_cast<const uint32_t*>(parent)[v];
+          vout = inv ? inv[v] : v;
+          const uint32_t cur = reinterpret_cast<const uint32_t*>(parent)[vout];
           if (cur > u) {
-            const uint32_t old = atomicMin(reinterpret_cast<uint32_t*>(parent) + v, u);
+            const uint32_t old = atomicMin(reinterpret_cast<uint32_t*>(parent) + vout, u);
             own = (old == 0xFFFFFFFFu);
           }
         }
       }
       int32_t deg = 0;
       if (own) {
-        if (level) level[v] = k;
+        if (level) level[vout] = k;
         if (mp.symmetric) mark[v] = level_tag(k);
         deg = (int32_t)(off[v + 1] - off[v]);
         ++my_reached;
@@ -390,7 +396,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, uint32_t* __restrict__ vis,
     int32_t* __restrict__ parent, int32_t* __restrict__ level, uint8_t* __restrict__ mark,
     Queues q, int32_t* __restrict__ jstart_base, int64_t njs, const int32_t* __restrict__ zq,
-    LevelState* st, int cbits, int64_t nwords, MarkPolicy mp) {
+    LevelState* st, int cbits, int64_t nwords, MarkPolicy mp, const int32_t* __restrict__ inv) {
   __shared__ long long s_wc[BLOCK / 64], s_wd[BLOCK / 64];
   __shared__ unsigned long long s_base;
   const int k = st->k_fold;
@@ -486,8 +492,9 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
           if (t[i] == tprev) p = u[i];
       }
       if (p >= 0 || d <= kSerialScan) {
-        parent[v] = p;
-        if (level) level[v] = k;
+        const int32_t vo = inv ? inv[v] : v;
+        parent[vo] = (inv && p >= 0) ? inv[p] : p;
+        if (level) level[vo] = k;
       } else {
         long_bits |= 1u << b;
       }
@@ -526,8 +533,9 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
         }
       }
       if (lane == leader) {
-        parent[v] = p;
-        if (level) level[v] = k;
+        const int32_t vo = inv ? inv[v] : v;
+        parent[vo] = (inv && p >= 0) ? inv[p] : p;
+        if (level) level[vo] = k;
         long_bits &= long_bits - 1;
       }
     }
@@ -629,6 +637,24 @@ __global__ void k_check_symmetric(int64_t n, int64_t nnz, const int64_t* __restr
   }
 }
 
+// Degree-ordered copy: row v' of the copy is row inv[v'] of the original with
+// every adjacency mapped through rank (order within the row unchanged, so it
+// stays ascending in original ids). One wave per row.
+__global__ void k_permute_rows(int64_t n, const int64_t* __restrict__ off,
+                               const int32_t* __restrict__ col, const int64_t* __restrict__ roff,
+                               const int32_t* __restrict__ inv, const int32_t* __restrict__ rank,
+                               int32_t* __restrict__ rcol) {
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int lane = lane_id();
+  for (int64_t v = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); v < n;
+       v += waves) {
+    const int64_t src = off[inv[v]];
+    const int64_t len = off[inv[v] + 1] - src;
+    const int64_t dst = roff[v];
+    for (int64_t i = lane; i < len; i += 64) rcol[dst + i] = rank[col[src + i]];
+  }
+}
+
 __global__ void k_widen_offsets(int64_t n1, const int32_t* __restrict__ src,
                                 int64_t* __restrict__ dst) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -681,6 +707,10 @@ void csr_free(bfs_graph* g) {
   (void)hipFree(c.state);
   (void)hipFree(c.tmp_parent);
   (void)hipFree(c.tmp_level);
+  (void)hipFree(c.roff);
+  (void)hipFree(c.rcol);
+  (void)hipFree(c.rank);
+  (void)hipFree(c.inv);
   c = CsrDev{};
 }
 
@@ -724,6 +754,45 @@ int csr_check_symmetric(bfs_graph* g, hipStream_t s, int* symmetric) {
   (void)hipFree(d_bad);
   if (e != hipSuccess) return hip_fail(e, "symmetry check");
   *symmetric = h == 0;
+  return BFS_OK;
+}
+
+int csr_relabel(bfs_graph* g, const int64_t* host_off, hipStream_t s) {
+  CsrDev& c = g->csr;
+  const int64_t n = c.n;
+  // counting sort by descending degree, ties by ascending id
+  int64_t maxdeg = 0;
+  for (int64_t v = 0; v < n; ++v) maxdeg = std::max(maxdeg, host_off[v + 1] - host_off[v]);
+  std::vector<int64_t> start((size_t)maxdeg + 2, 0);
+  for (int64_t v = 0; v < n; ++v) ++start[(size_t)(maxdeg - (host_off[v + 1] - host_off[v]))];
+  int64_t acc = 0;
+  for (size_t b = 0; b < start.size(); ++b) {
+    const int64_t t = start[b];
+    start[b] = acc;
+    acc += t;
+  }
+  std::vector<int32_t> inv((size_t)n), rank((size_t)n);
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t nv = start[(size_t)(maxdeg - (host_off[v + 1] - host_off[v]))]++;
+    inv[(size_t)nv] = (int32_t)v;
+    rank[(size_t)v] = (int32_t)nv;
+  }
+  std::vector<int64_t> roff((size_t)n + 1);
+  roff[0] = 0;
+  for (int64_t i = 0; i < n; ++i)
+    roff[(size_t)i + 1] = roff[(size_t)i] + (host_off[inv[(size_t)i] + 1] - host_off[inv[(size_t)i]]);
+  BFS_HIP(hipMalloc(&c.roff, (size_t)(n + 1) * 8));
+  BFS_HIP(hipMalloc(&c.rcol, (size_t)std::max<int64_t>(c.nnz, 1) * 4));
+  BFS_HIP(hipMalloc(&c.rank, (size_t)n * 4));
+  BFS_HIP(hipMalloc(&c.inv, (size_t)n * 4));
+  BFS_HIP(hipMemcpyAsync(c.roff, roff.data(), roff.size() * 8, hipMemcpyHostToDevice, s));
+  BFS_HIP(hipMemcpyAsync(c.rank, rank.data(), rank.size() * 4, hipMemcpyHostToDevice, s));
+  BFS_HIP(hipMemcpyAsync(c.inv, inv.data(), inv.size() * 4, hipMemcpyHostToDevice, s));
+  k_permute_rows<<<4096, 256, 0, s>>>(n, c.off, c.col, c.roff, c.inv, c.rank, c.rcol);
+  BFS_HIP(hipGetLastError());
+  BFS_HIP(hipStreamSynchronize(s));
+  c.relabeled = 1;
+  g->device_bytes += (n + 1) * 8 + std::max<int64_t>(c.nnz, 1) * 4 + n * 8;
   return BFS_OK;
 }
 
@@ -773,8 +842,12 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   }
   k_init<<<std::max(igrid, 1), ib, 0, s>>>(c.n, d_parent, d_level, c.vis, c.nwords,
                                            reinterpret_cast<uint4*>(c.mark));
-  k_seed<<<1, 1, 0, s>>>(c.off, root, d_parent, d_level, c.vis, mp.symmetric ? c.mark : nullptr,
-                         q, c.jstart, c.state, c.cbits);
+  // the level kernels read the degree-ordered copy when there is one
+  const int64_t* koff = c.relabeled ? c.roff : c.off;
+  const int32_t* kcol = c.relabeled ? c.rcol : c.col;
+  const int32_t* kinv = c.relabeled ? c.inv : nullptr;
+  k_seed<<<1, 1, 0, s>>>(koff, root, d_parent, d_level, c.vis, mp.symmetric ? c.mark : nullptr,
+                         q, c.jstart, c.state, c.cbits, c.relabeled ? c.rank : nullptr);
 
   // expand launch shape: mark super-tile of 2048 or 4096 edges
   const bool wide = g->opt.mark_tile == 4096;
@@ -805,16 +878,16 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
       }
       if (wide)
         k_expand<kExpandBlock, 4><<<ge, kExpandBlock, 0, s>>>(
-            c.off, c.col, c.vis, d_parent, d_level, c.mark, q, c.jstart, c.njstart, c.zq,
-            c.state, c.cbits, mp);
+            koff, kcol, c.vis, d_parent, d_level, c.mark, q, c.jstart, c.njstart, c.zq,
+            c.state, c.cbits, mp, kinv);
       else
         k_expand<kExpandBlock, 2><<<ge, kExpandBlock, 0, s>>>(
-            c.off, c.col, c.vis, d_parent, d_level, c.mark, q, c.jstart, c.njstart, c.zq,
-            c.state, c.cbits, mp);
+            koff, kcol, c.vis, d_parent, d_level, c.mark, q, c.jstart, c.njstart, c.zq,
+            c.state, c.cbits, mp, kinv);
       if (prof) BFS_HIP(hipEventRecord(g->ev[3 + 3 * k], s));
-      k_finish<kFinishBlock><<<gf, kFinishBlock, 0, s>>>(c.off, c.col, c.vis, d_parent, d_level,
+      k_finish<kFinishBlock><<<gf, kFinishBlock, 0, s>>>(koff, kcol, c.vis, d_parent, d_level,
                                                          c.mark, q, c.jstart, c.njstart, c.zq,
-                                                         c.state, c.cbits, c.nwords, mp);
+                                                         c.state, c.cbits, c.nwords, mp, kinv);
       if (prof) BFS_HIP(hipEventRecord(g->ev[4 + 3 * k], s));
       ++k;
     }

@@ -78,6 +78,14 @@ struct CsrDev {
   // host staging for host-pointer outputs
   int32_t* tmp_parent = nullptr;
   int32_t* tmp_level = nullptr;
+  // degree-ordered copy used by the level kernels (large graphs): new id =
+  // rank of the vertex by descending degree; each row keeps its adjacencies
+  // in ascending original id, mapped to new ids
+  int relabeled = 0;
+  int64_t* roff = nullptr;       // n + 1, rows in new order
+  int32_t* rcol = nullptr;       // nnz, new ids
+  int32_t* rank = nullptr;       // original id -> new id
+  int32_t* inv = nullptr;        // new id -> original id
 };
 
 struct DcscDev {
@@ -134,6 +142,8 @@ int csr_widen(const int32_t* d_src32, int64_t n1, int64_t* d_dst, hipStream_t s)
 void csr_free(bfs_graph* g);
 int csr_validate(bfs_graph* g, hipStream_t s);
 int csr_check_symmetric(bfs_graph* g, hipStream_t s, int* symmetric);
+// Builds the degree-ordered copy from the host row offsets.
+int csr_relabel(bfs_graph* g, const int64_t* host_off, hipStream_t s);
 int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStream_t s,
             bool sync);
 int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st);

@@ -244,3 +244,31 @@ def test_rmat22_config_sampled_roots():
         G.set_options(claim=claim)
         say(f"rmat22 claim mode {claim}")
         assert_bfs_equal(g, G, roots[8])
+
+
+def test_degree_ordered_copy_gives_identical_results():
+    """Graphs with n >= 2^20 get a degree-ordered copy for the level kernels;
+    outputs stay in the caller's ids and equal the oracle with and without it,
+    for both ways of resolving levels and for a directed graph."""
+    g = graphgen.rmat_csr(20, 16, 17)
+    roots = graphgen.roots(g, 3, 71)
+    Gr = B.Graph.from_csr(g.n, g.off, g.col, trusted=True, symmetric=True)
+    Gp = B.Graph.from_csr(g.n, g.off, g.col, trusted=True, symmetric=True, relabel=False)
+    for r in roots:
+        say(f"relabel rmat20 root {r}")
+        for claim in (1, 2, 3):
+            Gr.set_options(claim=claim)
+            Gp.set_options(claim=claim)
+            assert_bfs_equal(g, Gr, r, want_level=(claim != 2))
+            assert_bfs_equal(g, Gp, r, want_level=(claim != 1))
+    rng = np.random.default_rng(5)
+    n = 1 << 20
+    src, dst = rng.integers(0, n, 3 * n), rng.integers(0, n, 3 * n)
+    order = np.lexsort((dst, src))
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(np.bincount(src[order], minlength=n))
+    gd = graphgen.CSR(n, off, dst[order].astype(np.int32))
+    Gd = graph_on_device(gd)
+    for r in (0, 12345, n - 1):
+        say(f"relabel directed root {r}")
+        assert_bfs_equal(gd, Gd, r)

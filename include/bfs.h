@@ -100,7 +100,7 @@ typedef struct bfs_run_stats {
   int64_t edges_traversed;   /* adjacencies scanned = sum of degrees of reached vertices */
   int64_t reached;           /* vertices with level >= 0 */
   int64_t frontier_total;    /* sum of frontier sizes over all levels */
-  int32_t expand_launches;   /* expand-kernel launches, including empty speculative ones */
+  int32_t expand_launches;   /* levels enqueued, including empty speculative ones */
   int32_t mark_levels;       /* levels resolved by mark-and-resolve instead of atomicMin */
   double expand_ms;          /* summed device time of those launches (options.profile = 1) */
   double total_ms;           /* device time of the whole run (options.profile = 1) */
@@ -112,14 +112,16 @@ typedef struct bfs_options {
   int32_t batch_levels; /* levels enqueued between host checks in mode 1 */
   int32_t grid_blocks;  /* blocks of the expand kernel */
   int32_t lds_bitmap;   /* 1 = stage the visited bitmap in LDS when it fits */
-  int32_t profile;      /* 1 = time each expand launch with HIP events (-1 = off) */
+  int32_t profile;      /* 1 = time each level's expand and finish with HIP events (-1 = off) */
   int32_t claim;        /* how a level resolves its new vertices' parents:
                            3 = by frontier size (default), 1 = atomicMin claims always,
                            2 = mark-and-resolve whenever the graph is symmetric */
   int32_t claim_threshold; /* frontier edges from which a level uses mark-and-resolve
                               (0 = keep; default max(n / 64, 4096)) */
-  int32_t mark_tile;    /* edges per workgroup tile of mark-and-resolve expands: 2048 or
-                           4096 (0 = keep; default 2048) */
+  int32_t cold_probe;   /* mark-and-resolve expands, targets beyond the LDS-resident hot
+                           prefix of the visited bitmap: 1 = read the visited word, then
+                           store the touch mark; 2 = read the touch mark, store it when
+                           zero (0 = keep; default 2) */
 } bfs_options_t;
 
 /* ---------------------------------------------------------------- graphs */
@@ -185,8 +187,8 @@ typedef struct bfs_level_info {
   int32_t mark;         /* 1 = mark-and-resolve, 0 = atomicMin claims */
   int64_t frontier;     /* vertices of frontier k-1 that were expanded */
   int64_t edges;        /* their adjacencies */
-  double expand_ms;     /* device time of the expand launch */
-  double finish_ms;     /* device time of the finish launch */
+  double expand_ms;     /* device time of the level's expand launches (claim and mark) */
+  double finish_ms;     /* device time of its finish and resolve launches */
 } bfs_level_info_t;
 
 /*

@@ -67,7 +67,7 @@ class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch_levels", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("lds_bitmap", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("claim", ctypes.c_int32),
-                ("claim_threshold", ctypes.c_int32), ("mark_tile", ctypes.c_int32)]
+                ("claim_threshold", ctypes.c_int32), ("cold_probe", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -263,9 +263,9 @@ class Graph:
         return n.value, nnz.value, b.value
 
     def set_options(self, mode=0, batch_levels=0, grid_blocks=0, lds_bitmap=0, profile=0,
-                    claim=0, claim_threshold=0, mark_tile=0):
+                    claim=0, claim_threshold=0, cold_probe=0):
         o = Options(mode, batch_levels, grid_blocks, lds_bitmap, profile, claim, claim_threshold,
-                    mark_tile)
+                    cold_probe)
         _check(load().bfs_graph_set_options(self.handle, ctypes.byref(o)),
                "bfs_graph_set_options")
 

@@ -5,9 +5,9 @@
 // newly reached vertex takes the smallest frontier id among its neighbours
 // as its parent.
 //
-// One level k is two launches, both reading the level number and the
-// frontier counters from device memory (consecutive launches have identical
-// arguments; a level whose input frontier is empty exits at once, so the
+// One level k is up to four launches, all reading the level number and the
+// frontier counters from device memory (consecutive levels have identical
+// arguments; a launch whose level does not concern it exits at once, so the
 // host enqueues several levels between reads of the frontier size):
 //
 //   expand(k)  streams the adjacencies of frontier k-1 in edge-balanced
@@ -15,19 +15,23 @@
 //              edge to its row, so high-degree rows are split across tiles
 //              and workgroups) and tests the visited bitmap, then claims the
 //              unvisited targets in one of two ways, chosen per level from
-//              the frontier's edge count:
-//                claim  atomicMin on parent[]; the thread whose atomic turned
-//                       parent from -1 into a frontier id appends the vertex
-//                       to the next frontier (small frontiers: few atomics);
-//                mark   a plain byte store marks the target as touched; no
-//                       atomics per edge (large frontiers, symmetric graphs).
+//              the frontier's size:
+//                claim  (k_expand) atomicMin on parent[]; the thread whose
+//                       atomic turned parent from -1 into a frontier id
+//                       appends the vertex to the next frontier (small
+//                       frontiers: few atomics);
+//                mark   (k_expand_mark) the target is recorded as touched,
+//                       with no atomics per edge: in an LDS copy of the hot
+//                       prefix of the visited bitmap, or by a byte store
+//                       (large frontiers, symmetric graphs).
 //   finish(k)  claim levels: sets the visited bits of the new frontier.
-//              mark levels: scans the marks one 32-vertex word per thread,
-//              gives each marked vertex its level and its parent, which is
-//              the first neighbour one level up in its ascending adjacency
-//              list (for an undirected graph that is the minimum frontier
-//              id adjacent to it), appends it to the next frontier, sets
-//              the visited word and turns the marks into the level's tag.
+//              mark levels: collects the touched vertices one 32-vertex word
+//              per thread, appends them to the next frontier, sets their
+//              visited bits and gives them the level's tag.
+//   resolve(k) mark levels: gives each vertex of the new frontier its level
+//              and its parent, the first neighbour one level up in its
+//              ascending adjacency list (for an undirected graph that is the
+//              minimum frontier id adjacent to it).
 //
 // Both ways give the same parents: the unique minimum-id neighbour one
 // level up. Appends to the next frontier are aggregated per workgroup into
@@ -44,17 +48,17 @@ namespace {
 
 // jstart granularity and claim-path tile: 1024 edges (256 threads x 4)
 constexpr int kTileJ = 1024;
-// mark path: super-tiles of MSUB x 1024 edges (MSUB = 2 or 4, a launch
-// shape choice), MSUB * 4 edges per thread
-constexpr int kMarkSubMax = 4;
+// mark path: one 1024-thread workgroup per CU, each wave on its own
+// 1024-edge tiles
+constexpr int kMarkBlock = 1024;
+// Hot prefix of the visited bitmap kept in LDS by the mark path: the first
+// 39936 * 32 vertices (156 KiB of the CU's 160 KiB; the rest holds the
+// waves' row-start masks). In a degree-ordered copy these are the
+// highest-degree vertices, the targets of most probes.
+constexpr int kHotWordsMax = 39936;
 // mark-and-resolve: vertices of degree above this search their parent with
 // the whole wave instead of one thread
 constexpr int kSerialScan = 64;
-// LDS of the expand kernel: the larger of the two paths' needs (staged
-// row starts of a mark super-tile, or the claim path's rows and owners)
-template <int MSUB>
-constexpr int lds_bytes() { return (kTileJ * MSUB + 1) * 8; }
-static_assert((kTileJ + 1) * 8 + kTileJ * (4 + 4) <= lds_bytes<2>(), "claim path LDS");
 
 // Mark bytes: 0 = not reached, 1 = touched by the current level's frontier,
 // 2 + (level mod 3) = reached at that level. A neighbour of a vertex at level
@@ -165,6 +169,21 @@ __device__ __forceinline__ void block_scan2(long long c, long long d, long long*
   ex_d = bd + id - d;
 }
 
+// Position of the r-th (0-based) set bit of x; x has more than r set bits.
+__device__ __forceinline__ int select_bit(uint32_t x, int r) {
+  int pos = 0;
+  int c = __popc(x & 0xFFFFu);
+  if (r >= c) { r -= c; x >>= 16; pos += 16; }
+  c = __popc(x & 0xFFu);
+  if (r >= c) { r -= c; x >>= 8; pos += 8; }
+  c = __popc(x & 0xFu);
+  if (r >= c) { r -= c; x >>= 4; pos += 4; }
+  c = __popc(x & 0x3u);
+  if (r >= c) { r -= c; x >>= 2; pos += 2; }
+  if (r >= (int)(x & 1u)) pos += 1;
+  return pos;
+}
+
 // Map the edge tiles of the next level that start inside [e, e + d) to
 // queue entry j.
 __device__ __forceinline__ void map_tiles(int32_t* __restrict__ jstart, long long e, long long d,
@@ -172,7 +191,9 @@ __device__ __forceinline__ void map_tiles(int32_t* __restrict__ jstart, long lon
   for (long long w = (e + kTileJ - 1) / kTileJ; w * kTileJ < e + d; ++w) jstart[w] = j;
 }
 
-template <int BLOCK, int MSUB>
+// expand(k), claim levels; on a mark level it only does the level's
+// bookkeeping and leaves the edges to k_expand_mark.
+template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_expand(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const uint32_t* __restrict__ vis, int32_t* __restrict__ parent, int32_t* __restrict__ level,
@@ -180,11 +201,11 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     int32_t* __restrict__ zq, LevelState* st, int cbits, MarkPolicy mp,
     const int32_t* __restrict__ inv) {
   constexpr int WAVES = BLOCK / 64;
-  __shared__ __align__(16) unsigned char s_raw[lds_bytes<MSUB>()];
+  __shared__ __align__(16) long long s_qe[kTileJ + 1];
+  __shared__ int32_t s_ov[kTileJ], s_od[kTileJ];
   __shared__ long long s_wc[WAVES], s_wd[WAVES];
   __shared__ unsigned long long s_base;
   __shared__ int s_cnt;
-  long long* s_qe = reinterpret_cast<long long*>(s_raw);
 
   const int k = st->k_expand;
   const int kin = k - 1;
@@ -207,9 +228,9 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
       st->hist_mark[k] = mark_level(cin, cbits, mp) ? 1 : 0;
     }
   }
-  if (F == 0) return;
+  if (F == 0 || mark_level(cin, cbits, mp)) return;
   const int64_t njt = (T + kTileJ - 1) / kTileJ;   // jstart tiles of this level
-  // tile map of frontier k-1 (read) and of frontier k (written by the claim path)
+  // tile map of frontier k-1 (read) and of frontier k (written here)
   const int32_t* __restrict__ jstart = jstart_base + (int64_t)(kin & 1) * njs;
   int32_t* __restrict__ jstart_out = jstart_base + (int64_t)(k & 1) * njs;
   const int32_t* __restrict__ qv_in = q.qv[kin & 1];
@@ -217,54 +238,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   const int64_t* __restrict__ qe_in = q.qe[kin & 1];
   const int tid = threadIdx.x;
 
-  if (mark_level(cin, cbits, mp)) {
-    // ---------------------------------------------------------- mark path
-    constexpr int TILE = kTileJ * MSUB;
-    constexpr int kMarkItems = TILE / BLOCK;
-    const int64_t nitems = (T + TILE - 1) / TILE;
-    for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
-      const int64_t e0 = w * TILE;
-      const int64_t e1 = min(e0 + (int64_t)TILE, T);
-      const int32_t j0 = jstart[w * MSUB];
-      const int32_t j1 = ((w + 1) * MSUB < njt) ? jstart[(w + 1) * MSUB] : (int32_t)(F - 1);
-      const int R = j1 - j0 + 1;
-      for (int r = tid; r < R; r += BLOCK) s_qe[r] = qe_in[j0 + r];
-      __syncthreads();
-      int32_t vv[kMarkItems];
-#pragma unroll
-      for (int i = 0; i < kMarkItems; ++i) {
-        const int64_t e = e0 + (int64_t)i * BLOCK + tid;
-        vv[i] = -1;
-        if (e < e1) {
-          int lo = 0, hi = R - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_qe[mid] <= e) lo = mid; else hi = mid - 1;
-          }
-          vv[i] = col[qo_in[j0 + lo] + (e - s_qe[lo])];
-        }
-      }
-      uint32_t wv[kMarkItems];
-#pragma unroll
-      for (int i = 0; i < kMarkItems; ++i) wv[i] = vv[i] >= 0 ? vis[vv[i] >> 5] : 0xFFFFFFFFu;
-      uint8_t mk[kMarkItems];
-#pragma unroll
-      for (int i = 0; i < kMarkItems; ++i) {
-        const bool unvisited = vv[i] >= 0 && !((wv[i] >> (vv[i] & 31)) & 1u);
-        mk[i] = unvisited ? mark[vv[i]] : (uint8_t)1;
-      }
-#pragma unroll
-      for (int i = 0; i < kMarkItems; ++i)
-        if (mk[i] == 0) mark[vv[i]] = 1;
-      __syncthreads();
-    }
-    return;
-  }
-
-  // ------------------------------------------------------------ claim path
   constexpr int ITEMS = kTileJ / BLOCK;
-  int32_t* s_ov = reinterpret_cast<int32_t*>(s_raw + (kTileJ + 1) * 8);
-  int32_t* s_od = s_ov + kTileJ;
   int32_t* __restrict__ qv_out = q.qv[k & 1];
   int64_t* __restrict__ qo_out = q.qo[k & 1];
   int64_t* __restrict__ qe_out = q.qe[k & 1];
@@ -390,15 +364,144 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   }
 }
 
+// expand(k), mark levels. One 1024-thread workgroup per CU keeps the first
+// hw words of the visited bitmap in LDS for the whole level (the bitmap is
+// read-only until finish(k)). A target in that hot prefix sets its bit in the
+// LDS copy, which then also filters later touches of it by this workgroup; a
+// target beyond it is checked in global memory and, when neither visited nor
+// touched yet, gets a plain byte store of 1 in mark[] (an unvisited vertex's
+// byte holds 0 or 1, so concurrent stores agree). At the end each workgroup
+// writes the bits its LDS copy gained to its own slice of hot_new; finish(k)
+// ORs the slices.
+//
+// Each wave takes whole 1024-edge tiles on its own (no workgroup barrier per
+// tile). Lane l handles edges i*64 + l, i = 0..15. The row of an edge comes
+// from a 1024-bit mask of the tile's row starts: the number of starts at or
+// before the edge (mbcnt over the 64-bit window of step i plus a running
+// count), and its position in the row from the last start at or before it.
+//
+// COLD selects how targets beyond the hot prefix are tested: 0 reads the
+// visited word and stores the mark unconditionally when unvisited; 1 reads
+// the mark byte (nonzero = visited or touched) and stores only when zero.
+template <int COLD>
+__global__ __launch_bounds__(kMarkBlock) void k_expand_mark(
+    const int32_t* __restrict__ col, const uint32_t* __restrict__ vis,
+    uint8_t* __restrict__ mark, Queues q, const int32_t* __restrict__ jstart_base, int64_t njs,
+    const LevelState* __restrict__ st, int cbits, MarkPolicy mp, int hw,
+    uint32_t* __restrict__ hot_new) {
+  constexpr int WAVES = kMarkBlock / 64;
+  constexpr int STEPS = kTileJ / 64;   // edges per lane per tile
+  __shared__ uint32_t s_hot[kHotWordsMax];
+  __shared__ uint32_t s_starts[WAVES][kTileJ / 32];
+
+  const int k = st->k_expand;
+  const int kin = k - 1;
+  const unsigned long long cmask = (1ull << cbits) - 1;
+  const unsigned long long cin = st->ctr[kin % 3];
+  const int64_t F = (int64_t)(cin & cmask);
+  const int64_t T = (int64_t)(cin >> cbits);
+  if (F == 0 || !mark_level(cin, cbits, mp)) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < hw; i += kMarkBlock) s_hot[i] = vis[i];
+  __syncthreads();
+  const int64_t hotv = (int64_t)hw << 5;
+  const int64_t njt = (T + kTileJ - 1) / kTileJ;
+  const int32_t* __restrict__ jstart = jstart_base + (int64_t)(kin & 1) * njs;
+  const int64_t* __restrict__ qo_in = q.qo[kin & 1];
+  const int64_t* __restrict__ qe_in = q.qe[kin & 1];
+  const int wid = tid >> 6;
+  const int lane = lane_id();
+  uint32_t* __restrict__ starts = s_starts[wid];
+  const int64_t nwaves = (int64_t)gridDim.x * WAVES;
+  int64_t w = (int64_t)blockIdx.x * WAVES + wid;
+  int32_t j0n = 0, j1n = 0;
+  if (w < njt) {
+    j0n = jstart[w];
+    j1n = (w + 1 < njt) ? jstart[w + 1] : (int32_t)(F - 1);
+  }
+  for (; w < njt; w += nwaves) {
+    const int64_t e0 = w * kTileJ;
+    const int n_e = (int)min((int64_t)kTileJ, T - e0);
+    const int32_t j0 = j0n;
+    const int R = j1n - j0 + 1;   // rows are non-empty: R <= kTileJ + 1
+    // tile map of the wave's next tile, loaded early
+    const int64_t wn = w + nwaves;
+    if (wn < njt) {
+      j0n = jstart[wn];
+      j1n = (wn + 1 < njt) ? jstart[wn + 1] : (int32_t)(F - 1);
+    }
+    // row starts inside the tile (rows 1..R-1 start after e0)
+    if (lane < kTileJ / 32) starts[lane] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t row0_pos = e0 - qe_in[j0];   // position of the tile's first edge in row 0
+    for (int r = 1 + lane; r < R; r += 64) {
+      const int64_t rel = qe_in[j0 + r] - e0;
+      if (rel < n_e) atomicOr(&starts[rel >> 5], 1u << (rel & 31));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // row and position of each of the lane's edges
+    int32_t row[STEPS];
+    int64_t pos[STEPS];
+    {
+      int base = 0;          // row starts before this step's window
+      int64_t carry = row0_pos;   // position of the window's first edge in row `base`
+      const unsigned long long below = (2ull << lane) - 1;   // lanes 0..lane
+#pragma unroll
+      for (int i = 0; i < STEPS; ++i) {
+        const unsigned long long M =
+            (unsigned long long)starts[2 * i] | ((unsigned long long)starts[2 * i + 1] << 32);
+        const unsigned long long mb = M & below;
+        const int c = __popcll(mb);
+        row[i] = base + c;
+        pos[i] = c ? (int64_t)(lane - (63 - __clzll(mb))) : carry + lane;
+        base += __popcll(M);
+        // the next window's first edge: just past the last start seen, or 64
+        // further along the same row
+        carry = M ? (int64_t)(1 + __clzll(M)) : carry + 64;
+      }
+    }
+    int32_t vv[STEPS];
+#pragma unroll
+    for (int i = 0; i < STEPS; ++i) {
+      vv[i] = -1;
+      if (i * 64 + lane < n_e) vv[i] = col[qo_in[j0 + row[i]] + pos[i]];
+    }
+    uint32_t probe[STEPS];
+#pragma unroll
+    for (int i = 0; i < STEPS; ++i) {
+      probe[i] = 0xFFFFFFFFu;
+      if (vv[i] >= hotv) probe[i] = COLD ? (uint32_t)mark[vv[i]] : vis[vv[i] >> 5];
+    }
+#pragma unroll
+    for (int i = 0; i < STEPS; ++i) {
+      const int32_t v = vv[i];
+      if (v < 0) continue;
+      if (v < hotv)
+        atomicOr(&s_hot[v >> 5], 1u << (v & 31));
+      else if (COLD ? probe[i] == 0u : !((probe[i] >> (v & 31)) & 1u))
+        mark[v] = 1;
+    }
+  }
+  __syncthreads();
+  uint32_t* __restrict__ slice = hot_new + (int64_t)blockIdx.x * hw;
+  for (int i = tid; i < hw; i += kMarkBlock) slice[i] = s_hot[i] & ~vis[i];
+}
+
 // finish(k): see the header comment.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_finish(
-    const int64_t* __restrict__ off, const int32_t* __restrict__ col, uint32_t* __restrict__ vis,
-    int32_t* __restrict__ parent, int32_t* __restrict__ level, uint8_t* __restrict__ mark,
+    const int64_t* __restrict__ off, uint32_t* __restrict__ vis, uint8_t* __restrict__ mark,
     Queues q, int32_t* __restrict__ jstart_base, int64_t njs, const int32_t* __restrict__ zq,
-    LevelState* st, int cbits, int64_t nwords, MarkPolicy mp, const int32_t* __restrict__ inv) {
+    LevelState* st, int cbits, int64_t n, int64_t nwords, MarkPolicy mp, int hw,
+    const uint32_t* __restrict__ hot_new, int nslices) {
   __shared__ long long s_wc[BLOCK / 64], s_wd[BLOCK / 64];
   __shared__ unsigned long long s_base;
+  __shared__ int s_exw[BLOCK / 64][64];
+  __shared__ uint32_t s_m[BLOCK / 64][64];
   const int k = st->k_fold;
   const unsigned long long cmask = (1ull << cbits) - 1;
   const unsigned long long cin = st->ctr[(k - 1) % 3];
@@ -425,14 +528,16 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
     return;
   }
 
-  // mark level: resolve every marked vertex, one 32-vertex word per thread
+  // mark level: collect the touched vertices one 32-vertex word per thread
+  // (marks beyond the hot prefix, the OR of the expand workgroups' slices
+  // within it), append them to the next frontier in vertex order, set their
+  // visited bits and give them this level's tag. Parents come from k_resolve.
   int32_t* __restrict__ jstart = jstart_base + (int64_t)(k & 1) * njs;
   int32_t* __restrict__ qv_out = q.qv[k & 1];
   int64_t* __restrict__ qo_out = q.qo[k & 1];
   int64_t* __restrict__ qe_out = q.qe[k & 1];
   unsigned long long* ctr_out = &st->ctr[k % 3];
   uint4* __restrict__ mark4 = reinterpret_cast<uint4*>(mark);
-  const uint8_t tprev = level_tag(k - 1);
   const uint32_t tcur = level_tag(k);
   unsigned int my_reached = 0;
   for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nwords; base += stride) {
@@ -448,14 +553,39 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
 #pragma unroll
         for (int byte = 0; byte < 4; ++byte)
           if (((x[i] >> (8 * byte)) & 0xFFu) == 1u) m |= 1u << (4 * i + byte);
+      if (w < hw) {
+        uint32_t h[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        int s = 0;
+        for (; s + 8 <= nslices; s += 8)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) h[i] |= hot_new[(int64_t)(s + i) * hw + w];
+        for (; s < nslices; ++s) h[0] |= hot_new[(int64_t)s * hw + w];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m |= h[i];
+      }
     }
+    // row offsets of the word's 32 vertices, all loaded at once (the word's
+    // slice of off[] is 256-byte aligned; the last word may be partial)
+    int64_t o[33];
     long long cnt = __popc(m), dsum = 0;
-    // marked vertices whose parent was not among their first kSerialScan
-    // adjacencies: the wave finishes their search together
-    uint32_t long_bits = 0;
-    for (uint32_t bits = m; bits; bits &= bits - 1) {
-      const int64_t v = (w << 5) + (__ffs(bits) - 1);
-      dsum += off[v + 1] - off[v];
+    if (m) {
+      const int64_t vb = w << 5;
+      if (vb + 32 <= n) {
+        const longlong2* __restrict__ o2 = reinterpret_cast<const longlong2*>(off + vb);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const longlong2 t = o2[i];
+          o[2 * i] = t.x;
+          o[2 * i + 1] = t.y;
+        }
+        o[32] = off[vb + 32];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 33; ++i) o[i] = off[min(vb + i, n)];
+      }
+#pragma unroll
+      for (int b = 0; b < 32; ++b)
+        if ((m >> b) & 1u) dsum += o[b + 1] - o[b];
     }
     long long ex_c, ex_d, tot_c, tot_d;
     block_scan2<BLOCK>(cnt, dsum, s_wc, s_wd, ex_c, ex_d, tot_c, tot_d);
@@ -469,78 +599,48 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
     __syncthreads();
     const unsigned long long b0 = s_base;
     __syncthreads();
-    int64_t slot = (int64_t)(b0 & cmask) + ex_c;
-    long long epos = (long long)(b0 >> cbits) + ex_d;
-    for (uint32_t bits = m; bits; bits &= bits - 1) {
-      const int b = __ffs(bits) - 1;
-      const int32_t v = (int32_t)((w << 5) + b);
-      const int64_t o = off[v];
-      const int64_t d = off[v + 1] - o;
-      // parent: first neighbour one level up in the ascending adjacency,
-      // four adjacencies per step over the first kSerialScan of them
-      int32_t p = -1;
-      const int64_t lim = o + min(d, (int64_t)kSerialScan);
-      for (int64_t e = o; e < lim && p < 0; e += 4) {
-        int32_t u[4];
-        uint8_t t[4];
+    // The wave writes its entries in slot order, 64 consecutive slots per
+    // step (coalesced stores): entry i belongs to the lane whose count range
+    // holds it, and is the (i - start)-th marked vertex of that lane's word.
+    {
+      const int lane = lane_id();
+      const int wid = tid >> 6;
+      const long long c0 = __shfl(ex_c, 0, 64);     // the wave's first slot (block-relative)
+      const long long d0 = __shfl(ex_d, 0, 64);
+      const int wave_cnt = (int)(__shfl(ex_c + cnt, 63, 64) - c0);
+      s_exw[wid][lane] = (int)(ex_c - c0);
+      s_m[wid][lane] = m;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int64_t slot0 = (int64_t)(b0 & cmask) + c0;
+      long long epos = (long long)(b0 >> cbits) + d0;
+      const int64_t wbase = base + (wid << 6);      // word of lane 0
+      for (int r = 0; r < wave_cnt; r += 64) {
+        const int i = r + lane;
+        int64_t d = 0, o0 = 0;
+        int32_t v = 0;
+        if (i < wave_cnt) {
+          int lo = 0;   // last lane with s_exw <= i
 #pragma unroll
-        for (int i = 0; i < 4; ++i) u[i] = e + i < lim ? col[e + i] : 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) t[i] = e + i < lim ? mark[u[i]] : (uint8_t)0;
-#pragma unroll
-        for (int i = 3; i >= 0; --i)
-          if (t[i] == tprev) p = u[i];
-      }
-      if (p >= 0 || d <= kSerialScan) {
-        const int32_t vo = inv ? inv[v] : v;
-        parent[vo] = (inv && p >= 0) ? inv[p] : p;
-        if (level) level[vo] = k;
-      } else {
-        long_bits |= 1u << b;
-      }
-      qv_out[slot] = v;
-      qo_out[slot] = o;
-      qe_out[slot] = epos;
-      map_tiles(jstart, epos, d, (int32_t)slot);
-      ++slot;
-      epos += d;
-    }
-    // vertices not resolved by their first kSerialScan adjacencies: the wave
-    // scans the rest 64 adjacencies per step and takes the first
-    // (smallest-id) neighbour one level up
-    const int lane = lane_id();
-    for (;;) {
-      const unsigned long long pend = wave_ballot(long_bits != 0u);
-      if (!pend) break;
-      const int leader = __ffsll((long long)pend) - 1;
-      const int lb = long_bits ? __ffs(long_bits) - 1 : 0;
-      const int32_t v = __shfl((int32_t)((w << 5) + lb), leader, 64);
-      const int64_t o = off[v] + kSerialScan;
-      const int64_t end = off[v + 1];
-      int32_t p = -1;
-      for (int64_t base = o; base < end; base += 64) {
-        const int64_t e = base + lane;
-        int32_t u = 0;
-        bool hit = false;
-        if (e < end) {
-          u = col[e];
-          hit = mark[u] == tprev;
+          for (int step = 32; step; step >>= 1)
+            if (lo + step <= 63 && s_exw[wid][lo + step] <= i) lo += step;
+          v = (int32_t)(((wbase + lo) << 5) + select_bit(s_m[wid][lo], i - s_exw[wid][lo]));
+          o0 = off[v];
+          d = off[v + 1] - o0;
         }
-        const unsigned long long hb = wave_ballot(hit);
-        if (hb) {
-          p = __shfl(u, __ffsll((long long)hb) - 1, 64);
-          break;
+        const long long incl = wave_incl_scan(d);
+        const long long e = epos + incl - d;
+        if (i < wave_cnt) {
+          qv_out[slot0 + i] = v;
+          qo_out[slot0 + i] = o0;
+          qe_out[slot0 + i] = e;
+          map_tiles(jstart, e, d, (int32_t)(slot0 + i));
         }
-      }
-      if (lane == leader) {
-        const int32_t vo = inv ? inv[v] : v;
-        parent[vo] = (inv && p >= 0) ? inv[p] : p;
-        if (level) level[vo] = k;
-        long_bits &= long_bits - 1;
+        epos += __shfl(incl, 63, 64);
       }
     }
     if (m) {
-      // touched bytes become this level's tag
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
@@ -565,6 +665,143 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
     if (t) {
       atomicAdd(&st->reached, (unsigned long long)t);
       atomicMax(&st->depth, k);
+    }
+  }
+}
+
+// resolve(k), mark levels: the parent of each vertex of the new frontier is
+// its first neighbour one level up (tag of level k-1) in ascending adjacency
+// order, i.e. the minimum-id frontier vertex adjacent to it. Each thread takes
+// RV vertices at once and tests their first four adjacencies together, then
+// scans on four at a time up to kSerialScan; the wave finishes the longer
+// searches together, 64 adjacencies per step. For a large frontier the
+// workgroup first turns the tags of the hot prefix into an LDS bitmap of
+// level k-1, so most tests (hub neighbours) stay in LDS.
+constexpr int kResolveBlock = 1024;
+constexpr int kResolveRV = 4;
+
+__device__ __forceinline__ bool prev_level(int32_t u, int64_t hotv, const uint32_t* s_prev,
+                                           const uint8_t* __restrict__ mark, uint8_t tprev) {
+  return u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u : mark[u] == tprev;
+}
+
+__global__ __launch_bounds__(kResolveBlock) void k_resolve(
+    const int32_t* __restrict__ col, int32_t* __restrict__ parent, int32_t* __restrict__ level,
+    const uint8_t* __restrict__ mark, Queues q, const LevelState* __restrict__ st, int cbits,
+    MarkPolicy mp, const int32_t* __restrict__ inv, int hw) {
+  __shared__ uint32_t s_prev[kHotWordsMax];
+  const int k = st->k_fold;
+  const unsigned long long cmask = (1ull << cbits) - 1;
+  const unsigned long long cin = st->ctr[(k - 1) % 3];
+  if ((cin & cmask) == 0 || !mark_level(cin, cbits, mp)) return;
+  const unsigned long long c = st->ctr[k % 3];
+  const int64_t F = (int64_t)(c & cmask);
+  const int64_t T = (int64_t)(c >> cbits);
+  const int32_t* __restrict__ qv = q.qv[k & 1];
+  const int64_t* __restrict__ qo = q.qo[k & 1];
+  const int64_t* __restrict__ qe = q.qe[k & 1];
+  const uint8_t tprev = level_tag(k - 1);
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  // stage the hot prefix only when the frontier is large enough to repay it
+  const int64_t hotv = F >= ((int64_t)hw << 5) ? ((int64_t)hw << 5) : 0;
+  if (hotv) {
+    const uint4* __restrict__ mark4 = reinterpret_cast<const uint4*>(mark);
+    const uint32_t tp4 = 0x01010101u * tprev;
+    for (int i = tid; i < hw; i += kResolveBlock) {
+      const uint4 a = mark4[2 * i], b = mark4[2 * i + 1];
+      const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      uint32_t bits = 0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const uint32_t e = x[t] ^ tp4;   // zero bytes = tag tprev
+#pragma unroll
+        for (int byte = 0; byte < 4; ++byte)
+          if (((e >> (8 * byte)) & 0xFFu) == 0u) bits |= 1u << (4 * t + byte);
+      }
+      s_prev[i] = bits;
+    }
+    __syncthreads();
+  }
+  const int64_t chunk = (int64_t)kResolveBlock * kResolveRV;
+  const int64_t stride = (int64_t)gridDim.x * chunk;
+  for (int64_t base = (int64_t)blockIdx.x * chunk; base < F; base += stride) {
+    int32_t v[kResolveRV], p[kResolveRV];
+    int64_t o[kResolveRV], end[kResolveRV];
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t) {
+      const int64_t j = base + t * kResolveBlock + tid;
+      v[t] = -1;
+      p[t] = -1;
+      o[t] = end[t] = 0;
+      if (j < F) {
+        v[t] = qv[j];
+        o[t] = qo[j];
+        end[t] = o[t] + ((j + 1 < F ? qe[j + 1] : T) - qe[j]);
+      }
+    }
+    // first four adjacencies of all RV vertices together
+    int32_t u[kResolveRV][4];
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) u[t][i] = o[t] + i < end[t] ? col[o[t] + i] : -1;
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t)
+#pragma unroll
+      for (int i = 3; i >= 0; --i)
+        if (u[t][i] >= 0 && prev_level(u[t][i], hotv, s_prev, mark, tprev)) p[t] = u[t][i];
+    bool pending[kResolveRV];
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t) {
+      // serial continuation up to kSerialScan adjacencies
+      const int64_t lim = min(end[t], o[t] + (int64_t)kSerialScan);
+      for (int64_t e = o[t] + 4; e < lim && p[t] < 0; e += 4) {
+        int32_t w4[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w4[i] = e + i < lim ? col[e + i] : -1;
+#pragma unroll
+        for (int i = 3; i >= 0; --i)
+          if (w4[i] >= 0 && prev_level(w4[i], hotv, s_prev, mark, tprev)) p[t] = w4[i];
+      }
+      pending[t] = v[t] >= 0 && p[t] < 0 && end[t] - o[t] > kSerialScan;
+    }
+    // the wave scans the rest of each long adjacency list together
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t) {
+      for (;;) {
+        const unsigned long long pend = wave_ballot(pending[t]);
+        if (!pend) break;
+        const int leader = __ffsll((long long)pend) - 1;
+        const int64_t lo = shfl_ll(o[t] + kSerialScan, leader);
+        const int64_t hi = shfl_ll(end[t], leader);
+        int32_t found = -1;
+        for (int64_t e0 = lo; e0 < hi; e0 += 64) {
+          const int64_t e = e0 + lane;
+          int32_t uu = 0;
+          bool hit = false;
+          if (e < hi) {
+            uu = col[e];
+            hit = prev_level(uu, hotv, s_prev, mark, tprev);
+          }
+          const unsigned long long hb = wave_ballot(hit);
+          if (hb) {
+            found = __shfl(uu, __ffsll((long long)hb) - 1, 64);
+            break;
+          }
+        }
+        if (lane == leader) {
+          p[t] = found;
+          pending[t] = false;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t) {
+      if (v[t] < 0) continue;
+      const int32_t vo = inv ? inv[v[t]] : v[t];
+      parent[vo] = (inv && p[t] >= 0) ? inv[p[t]] : p[t];
+      if (level) level[vo] = k;
     }
   }
 }
@@ -670,7 +907,7 @@ constexpr int kFinishBlock = 256;
 int csr_alloc_workspace(bfs_graph* g) {
   CsrDev& c = g->csr;
   c.nwords = (c.n + 31) / 32;
-  c.njstart = c.nnz / kTileJ + 2 + kMarkSubMax;
+  c.njstart = c.nnz / kTileJ + 2;
   BFS_HIP(hipMalloc(&c.vis, (size_t)std::max<int64_t>(c.nwords, 1) * 4));
   for (int b = 0; b < 2; ++b) {
     BFS_HIP(hipMalloc(&c.qv[b], (size_t)c.n * 4));
@@ -685,6 +922,11 @@ int csr_alloc_workspace(bfs_graph* g) {
     BFS_HIP(hipMalloc(&c.mark, (size_t)std::max<int64_t>(c.nwords, 1) * 32));
     BFS_HIP(hipMemset(c.mark, 0, (size_t)std::max<int64_t>(c.nwords, 1) * 32));
     g->device_bytes += std::max<int64_t>(c.nwords, 1) * 32;
+    // one slice of hot-prefix bits per mark-path workgroup (one per CU)
+    c.hot_words = (int)std::min<int64_t>(std::max<int64_t>(c.nwords, 1), kHotWordsMax);
+    c.hot_slices = grid_for(g->device, (const void*)k_expand_mark<0>, kMarkBlock, 1);
+    BFS_HIP(hipMalloc(&c.hot_new, (size_t)c.hot_slices * c.hot_words * 4));
+    g->device_bytes += (int64_t)c.hot_slices * c.hot_words * 4;
   }
   g->device_bytes += std::max<int64_t>(c.nwords, 1) * 4 + c.n * 44 + c.njstart * 8 +
                      (int64_t)sizeof(LevelState);
@@ -704,6 +946,7 @@ void csr_free(bfs_graph* g) {
   (void)hipFree(c.jstart);
   (void)hipFree(c.zq);
   (void)hipFree(c.mark);
+  (void)hipFree(c.hot_new);
   (void)hipFree(c.state);
   (void)hipFree(c.tmp_parent);
   (void)hipFree(c.tmp_level);
@@ -849,15 +1092,18 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   k_seed<<<1, 1, 0, s>>>(koff, root, d_parent, d_level, c.vis, mp.symmetric ? c.mark : nullptr,
                          q, c.jstart, c.state, c.cbits, c.relabeled ? c.rank : nullptr);
 
-  // expand launch shape: mark super-tile of 2048 or 4096 edges
-  const bool wide = g->opt.mark_tile == 4096;
-  const void* kexp = wide ? (const void*)k_expand<kExpandBlock, 4>
-                          : (const void*)k_expand<kExpandBlock, 2>;
-  static int ge_cache[2] = {0, 0}, gf_cache = 0;
-  if (!ge_cache[wide]) ge_cache[wide] = grid_for(g->device, kexp, kExpandBlock, 8);
+  // launch shapes: the claim expand and finish fill the chip with 256-thread
+  // workgroups; the mark expand runs one 1024-thread workgroup per CU (its
+  // LDS holds the hot prefix of the visited bitmap)
+  const bool cold_mark = g->opt.cold_probe == 2;
+  static int ge_cache = 0, gf_cache = 0, gr_cache = 0;
+  if (!ge_cache) ge_cache = grid_for(g->device, (const void*)k_expand<kExpandBlock>, kExpandBlock, 8);
   if (!gf_cache) gf_cache = grid_for(g->device, (const void*)k_finish<kFinishBlock>, kFinishBlock, 4);
-  const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache[wide];
+  if (!gr_cache) gr_cache = grid_for(g->device, (const void*)k_resolve, kResolveBlock, 1);
+  const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache;
+  const int gm = g->opt.grid_blocks > 0 ? std::min(g->opt.grid_blocks, c.hot_slices) : c.hot_slices;
   const int gf = gf_cache;
+  const int gr = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : gr_cache;
   BFS_HIP(hipGetLastError());
 
   const int batch = g->opt.batch_levels > 0 ? g->opt.batch_levels : 4;
@@ -876,18 +1122,27 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
         }
         BFS_HIP(hipEventRecord(g->ev[2 + 3 * k], s));
       }
-      if (wide)
-        k_expand<kExpandBlock, 4><<<ge, kExpandBlock, 0, s>>>(
-            koff, kcol, c.vis, d_parent, d_level, c.mark, q, c.jstart, c.njstart, c.zq,
-            c.state, c.cbits, mp, kinv);
-      else
-        k_expand<kExpandBlock, 2><<<ge, kExpandBlock, 0, s>>>(
-            koff, kcol, c.vis, d_parent, d_level, c.mark, q, c.jstart, c.njstart, c.zq,
-            c.state, c.cbits, mp, kinv);
-      if (prof) BFS_HIP(hipEventRecord(g->ev[3 + 3 * k], s));
-      k_finish<kFinishBlock><<<gf, kFinishBlock, 0, s>>>(koff, kcol, c.vis, d_parent, d_level,
+      k_expand<kExpandBlock><<<ge, kExpandBlock, 0, s>>>(koff, kcol, c.vis, d_parent, d_level,
                                                          c.mark, q, c.jstart, c.njstart, c.zq,
-                                                         c.state, c.cbits, c.nwords, mp, kinv);
+                                                         c.state, c.cbits, mp, kinv);
+      if (mp.symmetric) {
+        if (cold_mark)
+          k_expand_mark<1><<<gm, kMarkBlock, 0, s>>>(kcol, c.vis, c.mark, q, c.jstart, c.njstart,
+                                                     c.state, c.cbits, mp, c.hot_words,
+                                                     c.hot_new);
+        else
+          k_expand_mark<0><<<gm, kMarkBlock, 0, s>>>(kcol, c.vis, c.mark, q, c.jstart, c.njstart,
+                                                     c.state, c.cbits, mp, c.hot_words,
+                                                     c.hot_new);
+      }
+      if (prof) BFS_HIP(hipEventRecord(g->ev[3 + 3 * k], s));
+      k_finish<kFinishBlock><<<gf, kFinishBlock, 0, s>>>(koff, c.vis, c.mark, q, c.jstart,
+                                                         c.njstart, c.zq, c.state, c.cbits,
+                                                         c.n, c.nwords, mp, c.hot_words,
+                                                         c.hot_new, gm);
+      if (mp.symmetric)
+        k_resolve<<<gr, kResolveBlock, 0, s>>>(kcol, d_parent, d_level, c.mark, q, c.state,
+                                               c.cbits, mp, kinv, c.hot_words);
       if (prof) BFS_HIP(hipEventRecord(g->ev[4 + 3 * k], s));
       ++k;
     }

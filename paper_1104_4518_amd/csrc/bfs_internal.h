@@ -72,6 +72,11 @@ struct CsrDev {
   int32_t* zq = nullptr;         // reached vertices of out-degree 0 (per level)
   uint8_t* mark = nullptr;       // per-vertex touch marks (nwords * 32 bytes)
   int symmetric = 0;             // undirected with ascending adjacency (checked or asserted)
+  // mark levels: hot prefix of the visited bitmap (words) and one slice of
+  // newly touched hot bits per mark-path workgroup
+  int hot_words = 0;
+  int hot_slices = 0;
+  uint32_t* hot_new = nullptr;
   int32_t* jstart = nullptr;     // first queue entry of each expand tile
   int64_t njstart = 0;
   LevelState* state = nullptr;

@@ -119,9 +119,10 @@ typedef struct bfs_options {
   int32_t claim_threshold; /* frontier edges from which a level uses mark-and-resolve
                               (0 = keep; default max(n / 64, 4096)) */
   int32_t cold_probe;   /* mark-and-resolve expands, targets beyond the LDS-resident hot
-                           prefix of the visited bitmap: 1 = read the visited word, then
-                           store the touch mark; 2 = read the touch mark, store it when
-                           zero (0 = keep; default 2) */
+                           prefix of the visited bitmap: 1 = read the touch-mark byte;
+                           2 = read the visited word first, the byte only when unvisited;
+                           3 = 2 once a quarter of the vertices is reached, else 1
+                           (0 = keep; default 3) */
 } bfs_options_t;
 
 /* ---------------------------------------------------------------- graphs */

@@ -51,7 +51,7 @@ void default_options(bfs_options_t* o) {
   o->profile = -1;
   o->claim = 3;
   o->claim_threshold = 0;
-  o->cold_probe = 2;
+  o->cold_probe = 3;
 }
 
 }  // namespace
@@ -230,8 +230,8 @@ int bfs_graph_set_options(bfs_graph_t* g, const bfs_options_t* opt) {
   if (opt->mode < 0 || opt->mode > 2 || opt->batch_levels < 0 || opt->grid_blocks < 0 ||
       opt->claim < 0 || opt->claim > 3 || opt->claim_threshold < 0)
     return fail(BFS_ERR_ARG, "option out of range");
-  if (opt->cold_probe && opt->cold_probe != 1 && opt->cold_probe != 2)
-    return fail(BFS_ERR_ARG, "cold_probe must be 1 or 2");
+  if (opt->cold_probe < 0 || opt->cold_probe > 3)
+    return fail(BFS_ERR_ARG, "cold_probe must be 1, 2 or 3");
   if (opt->cold_probe) g->opt.cold_probe = opt->cold_probe;
   if (opt->claim) g->opt.claim = opt->claim;
   if (opt->claim_threshold) g->opt.claim_threshold = opt->claim_threshold;

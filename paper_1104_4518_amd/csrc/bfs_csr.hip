@@ -364,6 +364,104 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   }
 }
 
+// Row data of one 1024-edge tile of the mark path: its first frontier entry
+// and row count (from the tile map) and, when it has at most 64 rows, lane
+// r's copy of row r's edge prefix and adjacency start.
+struct TileRows {
+  int32_t j0, R;
+  int64_t qe, qo;
+};
+
+// (w is the same for the whole wave, so are the values: readfirstlane lets
+// the compiler keep them, and the branches on them, scalar)
+__device__ __forceinline__ void tile_map(const int32_t* __restrict__ jstart, int64_t w,
+                                         int64_t njt, int64_t F, TileRows& t) {
+  const int32_t j0 = jstart[w];
+  const int32_t j1 = (w + 1 < njt) ? jstart[w + 1] : (int32_t)(F - 1);
+  t.j0 = __builtin_amdgcn_readfirstlane(j0);
+  t.R = __builtin_amdgcn_readfirstlane(j1 - j0 + 1);
+}
+
+__device__ __forceinline__ void tile_rows(const int64_t* __restrict__ qe_in,
+                                          const int64_t* __restrict__ qo_in, int lane,
+                                          TileRows& t) {
+  if (t.R <= 64 && lane < t.R) {
+    t.qe = qe_in[t.j0 + lane];
+    t.qo = qo_in[t.j0 + lane];
+  }
+}
+
+// Target vertex of each of the lane's STEPS edges of tile w (-1 past the
+// last edge): lane l takes edges i*64 + l. The row of an edge is the number
+// of row starts at or before it in the tile's 1024-bit start mask (per-wave
+// LDS), its position the distance from the last such start.
+template <int STEPS>
+__device__ __forceinline__ void tile_targets(const int32_t* __restrict__ col,
+                                             const int64_t* __restrict__ qe_in,
+                                             const int64_t* __restrict__ qo_in,
+                                             uint32_t* __restrict__ starts, int lane, int64_t w,
+                                             int64_t T, const TileRows& t, int32_t* vv) {
+  const int64_t e0 = w * kTileJ;
+  const int n_e = (int)min((int64_t)kTileJ, T - e0);
+  const bool staged = t.R <= 64;
+  if (lane < kTileJ / 32) starts[lane] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  int row0_pos;   // position of the tile's first edge in row 0
+  if (staged) {
+    row0_pos = (int)(e0 - shfl_ll(t.qe, 0));
+    if (lane >= 1 && lane < t.R) {
+      const int64_t rel = t.qe - e0;
+      if (rel < n_e) atomicOr(&starts[rel >> 5], 1u << (rel & 31));
+    }
+  } else {
+    row0_pos = (int)(e0 - qe_in[t.j0]);
+    for (int r = 1 + lane; r < t.R; r += 64) {
+      const int64_t rel = qe_in[t.j0 + r] - e0;
+      if (rel < n_e) atomicOr(&starts[rel >> 5], 1u << (rel & 31));
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // Row and position of each edge, then its target. A staged tile takes
+  // each row's adjacency start from the owning lane (an LDS-path shuffle, so
+  // the adjacency loads never wait on one another); a tile of more than 64
+  // rows gathers it from the queue. Edges past the tile's end load col[0]
+  // and are dropped.
+  const uint32_t lo_below = lane < 32 ? (2u << lane) - 1u : 0xFFFFFFFFu;
+  const uint32_t hi_below = lane < 32 ? 0u : (2u << (lane - 32)) - 1u;
+  int base = 0;            // row starts before this step's window
+  int carry = row0_pos;    // position of the window's first edge in row `base`
+  const int64_t* __restrict__ qo_t = qo_in + t.j0;
+#define BFS_TILE_STEP(ROW_START)                                                         \
+  for (int i = 0; i < STEPS; ++i) {                                                      \
+    const uint32_t mlo = starts[2 * i], mhi = starts[2 * i + 1];                         \
+    const uint32_t blo = mlo & lo_below, bhi = mhi & hi_below;                           \
+    const int c = __popc(blo) + __popc(bhi);                                             \
+    const int last = bhi ? 63 - __clz(bhi) : 31 - __clz(blo); /* last start <= lane */   \
+    const int row = base + c; /* <= number of starts <= R - 1 */                         \
+    const int pos = c ? lane - last : carry + lane;                                      \
+    base += __popc(mlo) + __popc(mhi);                                                   \
+    carry = mhi ? 64 - (63 - __clz(mhi)) : (mlo ? 64 - (31 - __clz(mlo)) : carry + 64); \
+    const bool ok = i * 64 + lane < n_e;                                                 \
+    const int64_t ro = (ROW_START);                                                      \
+    const int32_t x = col[ok ? ro + pos : 0];                                            \
+    vv[i] = ok ? x : -1;                                                                 \
+  }
+  // (carry: the next window's first edge is just past the last start seen,
+  // or 64 further along the same row)
+  if (staged) {
+#pragma unroll
+    BFS_TILE_STEP(shfl_ll(t.qo, row & 63))
+  } else {
+#pragma unroll
+    BFS_TILE_STEP(qo_t[row])
+  }
+#undef BFS_TILE_STEP
+}
+
 // expand(k), mark levels. One 1024-thread workgroup per CU keeps the first
 // hw words of the visited bitmap in LDS for the whole level (the bitmap is
 // read-only until finish(k)). A target in that hot prefix sets its bit in the
@@ -380,15 +478,17 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
 // before the edge (mbcnt over the 64-bit window of step i plus a running
 // count), and its position in the row from the last start at or before it.
 //
-// COLD selects how targets beyond the hot prefix are tested: 0 reads the
-// visited word and stores the mark unconditionally when unvisited; 1 reads
-// the mark byte (nonzero = visited or touched) and stores only when zero.
-template <int COLD>
+// A target beyond the hot prefix reads its mark byte (nonzero = visited or
+// touched) and stores 1 only when it is zero. Once a quarter of the graph is
+// reached (probe = 0), or always (probe = 2), the visited word is read first
+// and the mark byte only for an unvisited target: the bitmap is eight times
+// denser than the bytes and stays in L2, which pays once most targets are
+// visited. probe = 1 always reads the byte.
 __global__ __launch_bounds__(kMarkBlock) void k_expand_mark(
     const int32_t* __restrict__ col, const uint32_t* __restrict__ vis,
     uint8_t* __restrict__ mark, Queues q, const int32_t* __restrict__ jstart_base, int64_t njs,
     const LevelState* __restrict__ st, int cbits, MarkPolicy mp, int hw,
-    uint32_t* __restrict__ hot_new) {
+    uint32_t* __restrict__ hot_new, int64_t n, int probe) {
   constexpr int WAVES = kMarkBlock / 64;
   constexpr int STEPS = kTileJ / 64;   // edges per lane per tile
   __shared__ uint32_t s_hot[kHotWordsMax];
@@ -404,7 +504,8 @@ __global__ __launch_bounds__(kMarkBlock) void k_expand_mark(
   const int tid = threadIdx.x;
   for (int i = tid; i < hw; i += kMarkBlock) s_hot[i] = vis[i];
   __syncthreads();
-  const int64_t hotv = (int64_t)hw << 5;
+  const int32_t hot32 = hw << 5;
+  const bool visf = probe == 2 || (probe == 0 && (int64_t)st->reached * 4 >= n);
   const int64_t njt = (T + kTileJ - 1) / kTileJ;
   const int32_t* __restrict__ jstart = jstart_base + (int64_t)(kin & 1) * njs;
   const int64_t* __restrict__ qo_in = q.qo[kin & 1];
@@ -413,77 +514,69 @@ __global__ __launch_bounds__(kMarkBlock) void k_expand_mark(
   const int lane = lane_id();
   uint32_t* __restrict__ starts = s_starts[wid];
   const int64_t nwaves = (int64_t)gridDim.x * WAVES;
+  // Three-stage software pipeline over the wave's tiles t0, t1, t2, ...:
+  // while the probes of tile t0 are in flight, so are the adjacency loads of
+  // t1, the row data of t2 (lane r holds row r's edge prefix and adjacency
+  // start, for tiles of at most 64 rows) and the tile map of t3.
   int64_t w = (int64_t)blockIdx.x * WAVES + wid;
-  int32_t j0n = 0, j1n = 0;
   if (w < njt) {
-    j0n = jstart[w];
-    j1n = (w + 1 < njt) ? jstart[w + 1] : (int32_t)(F - 1);
-  }
-  for (; w < njt; w += nwaves) {
-    const int64_t e0 = w * kTileJ;
-    const int n_e = (int)min((int64_t)kTileJ, T - e0);
-    const int32_t j0 = j0n;
-    const int R = j1n - j0 + 1;   // rows are non-empty: R <= kTileJ + 1
-    // tile map of the wave's next tile, loaded early
-    const int64_t wn = w + nwaves;
-    if (wn < njt) {
-      j0n = jstart[wn];
-      j1n = (wn + 1 < njt) ? jstart[wn + 1] : (int32_t)(F - 1);
+    // A: row data of the next tile (loads in flight), B: tile map of the one
+    // after it
+    TileRows cur{}, A{}, B{};
+    tile_map(jstart, w, njt, F, cur);
+    tile_rows(qe_in, qo_in, lane, cur);
+    if (w + nwaves < njt) {
+      tile_map(jstart, w + nwaves, njt, F, A);
+      tile_rows(qe_in, qo_in, lane, A);
     }
-    // row starts inside the tile (rows 1..R-1 start after e0)
-    if (lane < kTileJ / 32) starts[lane] = 0u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int64_t row0_pos = e0 - qe_in[j0];   // position of the tile's first edge in row 0
-    for (int r = 1 + lane; r < R; r += 64) {
-      const int64_t rel = qe_in[j0 + r] - e0;
-      if (rel < n_e) atomicOr(&starts[rel >> 5], 1u << (rel & 31));
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // row and position of each of the lane's edges
-    int32_t row[STEPS];
-    int64_t pos[STEPS];
-    {
-      int base = 0;          // row starts before this step's window
-      int64_t carry = row0_pos;   // position of the window's first edge in row `base`
-      const unsigned long long below = (2ull << lane) - 1;   // lanes 0..lane
+    if (w + 2 * nwaves < njt) tile_map(jstart, w + 2 * nwaves, njt, F, B);
+    int32_t vv[STEPS], vn[STEPS];
+    tile_targets<STEPS>(col, qe_in, qo_in, starts, lane, w, T, cur, vv);
+    for (; w < njt; w += nwaves) {
+      const int64_t w1 = w + nwaves, w2 = w1 + nwaves, w3 = w2 + nwaves;
+      // stage 1: adjacency loads of the next tile
+      if (w1 < njt) tile_targets<STEPS>(col, qe_in, qo_in, starts, lane, w1, T, A, vn);
+      // stage 2: row data of the tile after it, tile map of the third
+      TileRows C{};
+      if (w2 < njt) {
+        tile_rows(qe_in, qo_in, lane, B);
+        if (w3 < njt) tile_map(jstart, w3, njt, F, C);
+      }
+      // stage 3: probes of this tile
+      uint32_t mk[STEPS];
+      if (visf) {
+        uint32_t wv[STEPS];
+#pragma unroll
+        for (int i = 0; i < STEPS; ++i) wv[i] = vv[i] >= hot32 ? vis[vv[i] >> 5] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int i = 0; i < STEPS; ++i)
+          mk[i] = (vv[i] >= hot32 && !((wv[i] >> (vv[i] & 31)) & 1u)) ? (uint32_t)mark[vv[i]] : 1u;
+      } else {
+#pragma unroll
+        for (int i = 0; i < STEPS; ++i) mk[i] = vv[i] >= hot32 ? (uint32_t)mark[vv[i]] : 1u;
+      }
+      // hot targets: read the LDS words first (most bits are already set:
+      // visited, or touched by this workgroup), then set the missing ones
+      uint32_t hb[STEPS];
+#pragma unroll
+      for (int i = 0; i < STEPS; ++i) hb[i] = (vv[i] >= 0 && vv[i] < hot32) ? s_hot[vv[i] >> 5] : 0xFFFFFFFFu;
 #pragma unroll
       for (int i = 0; i < STEPS; ++i) {
-        const unsigned long long M =
-            (unsigned long long)starts[2 * i] | ((unsigned long long)starts[2 * i + 1] << 32);
-        const unsigned long long mb = M & below;
-        const int c = __popcll(mb);
-        row[i] = base + c;
-        pos[i] = c ? (int64_t)(lane - (63 - __clzll(mb))) : carry + lane;
-        base += __popcll(M);
-        // the next window's first edge: just past the last start seen, or 64
-        // further along the same row
-        carry = M ? (int64_t)(1 + __clzll(M)) : carry + 64;
+        const int32_t v = vv[i];
+        if (v < 0) continue;
+        if (v < hot32) {
+          const uint32_t bit = 1u << (v & 31);
+          if (!(hb[i] & bit)) atomicOr(&s_hot[v >> 5], bit);
+        } else if (mk[i] == 0u) {
+          mark[v] = 1;
+        }
       }
-    }
-    int32_t vv[STEPS];
+      if (w1 < njt) {
 #pragma unroll
-    for (int i = 0; i < STEPS; ++i) {
-      vv[i] = -1;
-      if (i * 64 + lane < n_e) vv[i] = col[qo_in[j0 + row[i]] + pos[i]];
-    }
-    uint32_t probe[STEPS];
-#pragma unroll
-    for (int i = 0; i < STEPS; ++i) {
-      probe[i] = 0xFFFFFFFFu;
-      if (vv[i] >= hotv) probe[i] = COLD ? (uint32_t)mark[vv[i]] : vis[vv[i] >> 5];
-    }
-#pragma unroll
-    for (int i = 0; i < STEPS; ++i) {
-      const int32_t v = vv[i];
-      if (v < 0) continue;
-      if (v < hotv)
-        atomicOr(&s_hot[v >> 5], 1u << (v & 31));
-      else if (COLD ? probe[i] == 0u : !((probe[i] >> (v & 31)) & 1u))
-        mark[v] = 1;
+        for (int i = 0; i < STEPS; ++i) vv[i] = vn[i];
+      }
+      A = B;
+      B = C;
     }
   }
   __syncthreads();
@@ -672,13 +765,14 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
 // resolve(k), mark levels: the parent of each vertex of the new frontier is
 // its first neighbour one level up (tag of level k-1) in ascending adjacency
 // order, i.e. the minimum-id frontier vertex adjacent to it. Each thread takes
-// RV vertices at once and tests their first four adjacencies together, then
+// RV vertices at once and tests their first kFirst adjacencies together, then
 // scans on four at a time up to kSerialScan; the wave finishes the longer
 // searches together, 64 adjacencies per step. For a large frontier the
 // workgroup first turns the tags of the hot prefix into an LDS bitmap of
 // level k-1, so most tests (hub neighbours) stay in LDS.
 constexpr int kResolveBlock = 1024;
 constexpr int kResolveRV = 4;
+constexpr int kFirst = 8;
 
 __device__ __forceinline__ bool prev_level(int32_t u, int64_t hotv, const uint32_t* s_prev,
                                            const uint8_t* __restrict__ mark, uint8_t tprev) {
@@ -740,23 +834,42 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
         end[t] = o[t] + ((j + 1 < F ? qe[j + 1] : T) - qe[j]);
       }
     }
-    // first four adjacencies of all RV vertices together
-    int32_t u[kResolveRV][4];
+    // first kFirst adjacencies of all RV vertices together; the LDS tests of
+    // hot neighbours come first, so mark bytes are read only for the cold
+    // neighbours ahead of the first hot hit
+    int32_t u[kResolveRV][kFirst];
 #pragma unroll
     for (int t = 0; t < kResolveRV; ++t)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) u[t][i] = o[t] + i < end[t] ? col[o[t] + i] : -1;
+      for (int i = 0; i < kFirst; ++i) u[t][i] = o[t] + i < end[t] ? col[o[t] + i] : -1;
+    int hh[kResolveRV];
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t) {
+      hh[t] = kFirst;
+#pragma unroll
+      for (int i = kFirst - 1; i >= 0; --i)
+        if (u[t][i] >= 0 && u[t][i] < hotv && ((s_prev[u[t][i] >> 5] >> (u[t][i] & 31)) & 1u))
+          hh[t] = i;
+    }
+    uint8_t cm[kResolveRV][kFirst];
 #pragma unroll
     for (int t = 0; t < kResolveRV; ++t)
 #pragma unroll
-      for (int i = 3; i >= 0; --i)
-        if (u[t][i] >= 0 && prev_level(u[t][i], hotv, s_prev, mark, tprev)) p[t] = u[t][i];
+      for (int i = 0; i < kFirst; ++i)
+        cm[t][i] = (i < hh[t] && u[t][i] >= hotv) ? mark[u[t][i]] : (uint8_t)0;
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t) {
+      p[t] = hh[t] < kFirst ? u[t][hh[t] < kFirst ? hh[t] : 0] : -1;
+#pragma unroll
+      for (int i = kFirst - 1; i >= 0; --i)
+        if (i < hh[t] && cm[t][i] == tprev) p[t] = u[t][i];
+    }
     bool pending[kResolveRV];
 #pragma unroll
     for (int t = 0; t < kResolveRV; ++t) {
       // serial continuation up to kSerialScan adjacencies
       const int64_t lim = min(end[t], o[t] + (int64_t)kSerialScan);
-      for (int64_t e = o[t] + 4; e < lim && p[t] < 0; e += 4) {
+      for (int64_t e = o[t] + kFirst; e < lim && p[t] < 0; e += 4) {
         int32_t w4[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) w4[i] = e + i < lim ? col[e + i] : -1;
@@ -924,7 +1037,7 @@ int csr_alloc_workspace(bfs_graph* g) {
     g->device_bytes += std::max<int64_t>(c.nwords, 1) * 32;
     // one slice of hot-prefix bits per mark-path workgroup (one per CU)
     c.hot_words = (int)std::min<int64_t>(std::max<int64_t>(c.nwords, 1), kHotWordsMax);
-    c.hot_slices = grid_for(g->device, (const void*)k_expand_mark<0>, kMarkBlock, 1);
+    c.hot_slices = grid_for(g->device, (const void*)k_expand_mark, kMarkBlock, 1);
     BFS_HIP(hipMalloc(&c.hot_new, (size_t)c.hot_slices * c.hot_words * 4));
     g->device_bytes += (int64_t)c.hot_slices * c.hot_words * 4;
   }
@@ -1095,7 +1208,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   // launch shapes: the claim expand and finish fill the chip with 256-thread
   // workgroups; the mark expand runs one 1024-thread workgroup per CU (its
   // LDS holds the hot prefix of the visited bitmap)
-  const bool cold_mark = g->opt.cold_probe == 2;
+
   static int ge_cache = 0, gf_cache = 0, gr_cache = 0;
   if (!ge_cache) ge_cache = grid_for(g->device, (const void*)k_expand<kExpandBlock>, kExpandBlock, 8);
   if (!gf_cache) gf_cache = grid_for(g->device, (const void*)k_finish<kFinishBlock>, kFinishBlock, 4);
@@ -1126,14 +1239,9 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
                                                          c.mark, q, c.jstart, c.njstart, c.zq,
                                                          c.state, c.cbits, mp, kinv);
       if (mp.symmetric) {
-        if (cold_mark)
-          k_expand_mark<1><<<gm, kMarkBlock, 0, s>>>(kcol, c.vis, c.mark, q, c.jstart, c.njstart,
-                                                     c.state, c.cbits, mp, c.hot_words,
-                                                     c.hot_new);
-        else
-          k_expand_mark<0><<<gm, kMarkBlock, 0, s>>>(kcol, c.vis, c.mark, q, c.jstart, c.njstart,
-                                                     c.state, c.cbits, mp, c.hot_words,
-                                                     c.hot_new);
+        k_expand_mark<<<gm, kMarkBlock, 0, s>>>(kcol, c.vis, c.mark, q, c.jstart, c.njstart,
+                                                c.state, c.cbits, mp, c.hot_words, c.hot_new,
+                                                c.n, g->opt.cold_probe == 3 ? 0 : g->opt.cold_probe);
       }
       if (prof) BFS_HIP(hipEventRecord(g->ev[3 + 3 * k], s));
       k_finish<kFinishBlock><<<gf, kFinishBlock, 0, s>>>(koff, c.vis, c.mark, q, c.jstart,

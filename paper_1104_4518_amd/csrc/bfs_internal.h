@@ -77,6 +77,7 @@ struct CsrDev {
   int hot_words = 0;
   int hot_slices = 0;
   uint32_t* hot_new = nullptr;
+
   int32_t* jstart = nullptr;     // first queue entry of each expand tile
   int64_t njstart = 0;
   LevelState* state = nullptr;

@@ -102,7 +102,9 @@ typedef struct bfs_run_stats {
   int64_t frontier_total;    /* sum of frontier sizes over all levels */
   int32_t expand_launches;   /* levels enqueued, including empty speculative ones */
   int32_t mark_levels;       /* levels resolved by mark-and-resolve instead of atomicMin */
-  double expand_ms;          /* summed device time of those launches (options.profile = 1) */
+  double expand_ms;          /* summed device time of the levels' expand launches, claim and
+                                mark kernels (options.profile = 1) */
+  double mark_ms;            /* the mark-and-resolve expand kernel's share of expand_ms */
   double total_ms;           /* device time of the whole run (options.profile = 1) */
 } bfs_run_stats_t;
 
@@ -118,6 +120,8 @@ typedef struct bfs_options {
                            2 = mark-and-resolve whenever the graph is symmetric */
   int32_t claim_threshold; /* frontier edges from which a level uses mark-and-resolve
                               (0 = keep; default max(n / 64, 4096)) */
+  int32_t claim_min_frontier; /* frontier vertices from which a level uses mark-and-resolve
+                                 (0 = keep; default n / 1024 clamped to [1024, 4096]) */
   int32_t cold_probe;   /* mark-and-resolve expands, targets beyond the LDS-resident hot
                            prefix of the visited bitmap: 1 = read the touch-mark byte;
                            2 = read the visited word first, the byte only when unvisited;
@@ -189,6 +193,7 @@ typedef struct bfs_level_info {
   int64_t frontier;     /* vertices of frontier k-1 that were expanded */
   int64_t edges;        /* their adjacencies */
   double expand_ms;     /* device time of the level's expand launches (claim and mark) */
+  double mark_ms;       /* the mark expand kernel's share of expand_ms */
   double finish_ms;     /* device time of its finish and resolve launches */
 } bfs_level_info_t;
 

@@ -51,6 +51,7 @@ void default_options(bfs_options_t* o) {
   o->profile = -1;
   o->claim = 3;
   o->claim_threshold = 0;
+  o->claim_min_frontier = 0;
   o->cold_probe = 3;
 }
 
@@ -228,13 +229,15 @@ int bfs_graph_info(const bfs_graph_t* g, int64_t* n, int64_t* nnz, int64_t* devi
 int bfs_graph_set_options(bfs_graph_t* g, const bfs_options_t* opt) {
   if (!g || !opt) return fail(BFS_ERR_ARG, "NULL argument");
   if (opt->mode < 0 || opt->mode > 2 || opt->batch_levels < 0 || opt->grid_blocks < 0 ||
-      opt->claim < 0 || opt->claim > 3 || opt->claim_threshold < 0)
+      opt->claim < 0 || opt->claim > 3 || opt->claim_threshold < 0 ||
+      opt->claim_min_frontier < 0)
     return fail(BFS_ERR_ARG, "option out of range");
   if (opt->cold_probe < 0 || opt->cold_probe > 3)
     return fail(BFS_ERR_ARG, "cold_probe must be 1, 2 or 3");
   if (opt->cold_probe) g->opt.cold_probe = opt->cold_probe;
   if (opt->claim) g->opt.claim = opt->claim;
   if (opt->claim_threshold) g->opt.claim_threshold = opt->claim_threshold;
+  if (opt->claim_min_frontier) g->opt.claim_min_frontier = opt->claim_min_frontier;
   if (opt->mode) g->opt.mode = opt->mode;
   if (opt->batch_levels) g->opt.batch_levels = opt->batch_levels;
   if (opt->grid_blocks) g->opt.grid_blocks = opt->grid_blocks;

@@ -20,7 +20,7 @@
 //                       atomic turned parent from -1 into a frontier id
 //                       appends the vertex to the next frontier (small
 //                       frontiers: few atomics);
-//                mark   (k_expand_mark) the target is recorded as touched,
+//                mark   (k_expand_mark, bfs_mark.hip) the target is recorded as touched,
 //                       with no atomics per edge: in an LDS copy of the hot
 //                       prefix of the visited bitmap, or by a byte store
 //                       (large frontiers, symmetric graphs).
@@ -38,6 +38,7 @@
 // one atomic on a packed (edge total, vertex count) counter, which also
 // yields the degree prefix the next level needs to split its work by edges.
 #include "bfs_internal.h"
+#include "bfs_level.h"
 
 #include <algorithm>
 #include <cstddef>
@@ -45,48 +46,6 @@
 
 namespace bfsi {
 namespace {
-
-// jstart granularity and claim-path tile: 1024 edges (256 threads x 4)
-constexpr int kTileJ = 1024;
-// mark path: one 1024-thread workgroup per CU, each wave on its own
-// 1024-edge tiles
-constexpr int kMarkBlock = 1024;
-// Hot prefix of the visited bitmap kept in LDS by the mark path: the first
-// 39936 * 32 vertices (156 KiB of the CU's 160 KiB; the rest holds the
-// waves' row-start masks). In a degree-ordered copy these are the
-// highest-degree vertices, the targets of most probes.
-constexpr int kHotWordsMax = 39936;
-// mark-and-resolve: vertices of degree above this search their parent with
-// the whole wave instead of one thread
-constexpr int kSerialScan = 64;
-
-// Mark bytes: 0 = not reached, 1 = touched by the current level's frontier,
-// 2 + (level mod 3) = reached at that level. A neighbour of a vertex at level
-// k lies at level k-1, k or k+1 (or is unreached), so the tag identifies
-// "one level up" exactly.
-__device__ __forceinline__ uint8_t level_tag(int k) { return (uint8_t)(2 + k % 3); }
-
-struct Queues {
-  int32_t* qv[2];
-  int64_t* qo[2];
-  int64_t* qe[2];
-};
-
-// Level selection: mark-and-resolve when the graph is symmetric and the
-// input frontier is large in both edges and vertices (a small frontier makes
-// every new vertex search far for one of its few frontier neighbours).
-struct MarkPolicy {
-  int symmetric;
-  long long min_edges;
-  long long min_vertices;
-};
-
-__device__ __forceinline__ bool mark_level(unsigned long long cin, int cbits,
-                                           const MarkPolicy& mp) {
-  const unsigned long long cmask = (1ull << cbits) - 1;
-  return mp.symmetric && (long long)(cin >> cbits) >= mp.min_edges &&
-         (long long)(cin & cmask) >= mp.min_vertices;
-}
 
 __global__ void k_init(int64_t n, int32_t* __restrict__ parent, int32_t* __restrict__ level,
                        uint32_t* __restrict__ vis, int64_t nwords, uint4* __restrict__ mark) {
@@ -364,226 +323,6 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   }
 }
 
-// Row data of one 1024-edge tile of the mark path: its first frontier entry
-// and row count (from the tile map) and, when it has at most 64 rows, lane
-// r's copy of row r's edge prefix and adjacency start.
-struct TileRows {
-  int32_t j0, R;
-  int64_t qe, qo;
-};
-
-// (w is the same for the whole wave, so are the values: readfirstlane lets
-// the compiler keep them, and the branches on them, scalar)
-__device__ __forceinline__ void tile_map(const int32_t* __restrict__ jstart, int64_t w,
-                                         int64_t njt, int64_t F, TileRows& t) {
-  const int32_t j0 = jstart[w];
-  const int32_t j1 = (w + 1 < njt) ? jstart[w + 1] : (int32_t)(F - 1);
-  t.j0 = __builtin_amdgcn_readfirstlane(j0);
-  t.R = __builtin_amdgcn_readfirstlane(j1 - j0 + 1);
-}
-
-__device__ __forceinline__ void tile_rows(const int64_t* __restrict__ qe_in,
-                                          const int64_t* __restrict__ qo_in, int lane,
-                                          TileRows& t) {
-  if (t.R <= 64 && lane < t.R) {
-    t.qe = qe_in[t.j0 + lane];
-    t.qo = qo_in[t.j0 + lane];
-  }
-}
-
-// Target vertex of each of the lane's STEPS edges of tile w (-1 past the
-// last edge): lane l takes edges i*64 + l. The row of an edge is the number
-// of row starts at or before it in the tile's 1024-bit start mask (per-wave
-// LDS), its position the distance from the last such start.
-template <int STEPS>
-__device__ __forceinline__ void tile_targets(const int32_t* __restrict__ col,
-                                             const int64_t* __restrict__ qe_in,
-                                             const int64_t* __restrict__ qo_in,
-                                             uint32_t* __restrict__ starts, int lane, int64_t w,
-                                             int64_t T, const TileRows& t, int32_t* vv) {
-  const int64_t e0 = w * kTileJ;
-  const int n_e = (int)min((int64_t)kTileJ, T - e0);
-  const bool staged = t.R <= 64;
-  if (lane < kTileJ / 32) starts[lane] = 0u;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  int row0_pos;   // position of the tile's first edge in row 0
-  if (staged) {
-    row0_pos = (int)(e0 - shfl_ll(t.qe, 0));
-    if (lane >= 1 && lane < t.R) {
-      const int64_t rel = t.qe - e0;
-      if (rel < n_e) atomicOr(&starts[rel >> 5], 1u << (rel & 31));
-    }
-  } else {
-    row0_pos = (int)(e0 - qe_in[t.j0]);
-    for (int r = 1 + lane; r < t.R; r += 64) {
-      const int64_t rel = qe_in[t.j0 + r] - e0;
-      if (rel < n_e) atomicOr(&starts[rel >> 5], 1u << (rel & 31));
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // Row and position of each edge, then its target. A staged tile takes
-  // each row's adjacency start from the owning lane (an LDS-path shuffle, so
-  // the adjacency loads never wait on one another); a tile of more than 64
-  // rows gathers it from the queue. Edges past the tile's end load col[0]
-  // and are dropped.
-  const uint32_t lo_below = lane < 32 ? (2u << lane) - 1u : 0xFFFFFFFFu;
-  const uint32_t hi_below = lane < 32 ? 0u : (2u << (lane - 32)) - 1u;
-  int base = 0;            // row starts before this step's window
-  int carry = row0_pos;    // position of the window's first edge in row `base`
-  const int64_t* __restrict__ qo_t = qo_in + t.j0;
-#define BFS_TILE_STEP(ROW_START)                                                         \
-  for (int i = 0; i < STEPS; ++i) {                                                      \
-    const uint32_t mlo = starts[2 * i], mhi = starts[2 * i + 1];                         \
-    const uint32_t blo = mlo & lo_below, bhi = mhi & hi_below;                           \
-    const int c = __popc(blo) + __popc(bhi);                                             \
-    const int last = bhi ? 63 - __clz(bhi) : 31 - __clz(blo); /* last start <= lane */   \
-    const int row = base + c; /* <= number of starts <= R - 1 */                         \
-    const int pos = c ? lane - last : carry + lane;                                      \
-    base += __popc(mlo) + __popc(mhi);                                                   \
-    carry = mhi ? 64 - (63 - __clz(mhi)) : (mlo ? 64 - (31 - __clz(mlo)) : carry + 64); \
-    const bool ok = i * 64 + lane < n_e;                                                 \
-    const int64_t ro = (ROW_START);                                                      \
-    const int32_t x = col[ok ? ro + pos : 0];                                            \
-    vv[i] = ok ? x : -1;                                                                 \
-  }
-  // (carry: the next window's first edge is just past the last start seen,
-  // or 64 further along the same row)
-  if (staged) {
-#pragma unroll
-    BFS_TILE_STEP(shfl_ll(t.qo, row & 63))
-  } else {
-#pragma unroll
-    BFS_TILE_STEP(qo_t[row])
-  }
-#undef BFS_TILE_STEP
-}
-
-// expand(k), mark levels. One 1024-thread workgroup per CU keeps the first
-// hw words of the visited bitmap in LDS for the whole level (the bitmap is
-// read-only until finish(k)). A target in that hot prefix sets its bit in the
-// LDS copy, which then also filters later touches of it by this workgroup; a
-// target beyond it is checked in global memory and, when neither visited nor
-// touched yet, gets a plain byte store of 1 in mark[] (an unvisited vertex's
-// byte holds 0 or 1, so concurrent stores agree). At the end each workgroup
-// writes the bits its LDS copy gained to its own slice of hot_new; finish(k)
-// ORs the slices.
-//
-// Each wave takes whole 1024-edge tiles on its own (no workgroup barrier per
-// tile). Lane l handles edges i*64 + l, i = 0..15. The row of an edge comes
-// from a 1024-bit mask of the tile's row starts: the number of starts at or
-// before the edge (mbcnt over the 64-bit window of step i plus a running
-// count), and its position in the row from the last start at or before it.
-//
-// A target beyond the hot prefix reads its mark byte (nonzero = visited or
-// touched) and stores 1 only when it is zero. Once a quarter of the graph is
-// reached (probe = 0), or always (probe = 2), the visited word is read first
-// and the mark byte only for an unvisited target: the bitmap is eight times
-// denser than the bytes and stays in L2, which pays once most targets are
-// visited. probe = 1 always reads the byte.
-__global__ __launch_bounds__(kMarkBlock) void k_expand_mark(
-    const int32_t* __restrict__ col, const uint32_t* __restrict__ vis,
-    uint8_t* __restrict__ mark, Queues q, const int32_t* __restrict__ jstart_base, int64_t njs,
-    const LevelState* __restrict__ st, int cbits, MarkPolicy mp, int hw,
-    uint32_t* __restrict__ hot_new, int64_t n, int probe) {
-  constexpr int WAVES = kMarkBlock / 64;
-  constexpr int STEPS = kTileJ / 64;   // edges per lane per tile
-  __shared__ uint32_t s_hot[kHotWordsMax];
-  __shared__ uint32_t s_starts[WAVES][kTileJ / 32];
-
-  const int k = st->k_expand;
-  const int kin = k - 1;
-  const unsigned long long cmask = (1ull << cbits) - 1;
-  const unsigned long long cin = st->ctr[kin % 3];
-  const int64_t F = (int64_t)(cin & cmask);
-  const int64_t T = (int64_t)(cin >> cbits);
-  if (F == 0 || !mark_level(cin, cbits, mp)) return;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < hw; i += kMarkBlock) s_hot[i] = vis[i];
-  __syncthreads();
-  const int32_t hot32 = hw << 5;
-  const bool visf = probe == 2 || (probe == 0 && (int64_t)st->reached * 4 >= n);
-  const int64_t njt = (T + kTileJ - 1) / kTileJ;
-  const int32_t* __restrict__ jstart = jstart_base + (int64_t)(kin & 1) * njs;
-  const int64_t* __restrict__ qo_in = q.qo[kin & 1];
-  const int64_t* __restrict__ qe_in = q.qe[kin & 1];
-  const int wid = tid >> 6;
-  const int lane = lane_id();
-  uint32_t* __restrict__ starts = s_starts[wid];
-  const int64_t nwaves = (int64_t)gridDim.x * WAVES;
-  // Three-stage software pipeline over the wave's tiles t0, t1, t2, ...:
-  // while the probes of tile t0 are in flight, so are the adjacency loads of
-  // t1, the row data of t2 (lane r holds row r's edge prefix and adjacency
-  // start, for tiles of at most 64 rows) and the tile map of t3.
-  int64_t w = (int64_t)blockIdx.x * WAVES + wid;
-  if (w < njt) {
-    // A: row data of the next tile (loads in flight), B: tile map of the one
-    // after it
-    TileRows cur{}, A{}, B{};
-    tile_map(jstart, w, njt, F, cur);
-    tile_rows(qe_in, qo_in, lane, cur);
-    if (w + nwaves < njt) {
-      tile_map(jstart, w + nwaves, njt, F, A);
-      tile_rows(qe_in, qo_in, lane, A);
-    }
-    if (w + 2 * nwaves < njt) tile_map(jstart, w + 2 * nwaves, njt, F, B);
-    int32_t vv[STEPS], vn[STEPS];
-    tile_targets<STEPS>(col, qe_in, qo_in, starts, lane, w, T, cur, vv);
-    for (; w < njt; w += nwaves) {
-      const int64_t w1 = w + nwaves, w2 = w1 + nwaves, w3 = w2 + nwaves;
-      // stage 1: adjacency loads of the next tile
-      if (w1 < njt) tile_targets<STEPS>(col, qe_in, qo_in, starts, lane, w1, T, A, vn);
-      // stage 2: row data of the tile after it, tile map of the third
-      TileRows C{};
-      if (w2 < njt) {
-        tile_rows(qe_in, qo_in, lane, B);
-        if (w3 < njt) tile_map(jstart, w3, njt, F, C);
-      }
-      // stage 3: probes of this tile
-      uint32_t mk[STEPS];
-      if (visf) {
-        uint32_t wv[STEPS];
-#pragma unroll
-        for (int i = 0; i < STEPS; ++i) wv[i] = vv[i] >= hot32 ? vis[vv[i] >> 5] : 0xFFFFFFFFu;
-#pragma unroll
-        for (int i = 0; i < STEPS; ++i)
-          mk[i] = (vv[i] >= hot32 && !((wv[i] >> (vv[i] & 31)) & 1u)) ? (uint32_t)mark[vv[i]] : 1u;
-      } else {
-#pragma unroll
-        for (int i = 0; i < STEPS; ++i) mk[i] = vv[i] >= hot32 ? (uint32_t)mark[vv[i]] : 1u;
-      }
-      // hot targets: read the LDS words first (most bits are already set:
-      // visited, or touched by this workgroup), then set the missing ones
-      uint32_t hb[STEPS];
-#pragma unroll
-      for (int i = 0; i < STEPS; ++i) hb[i] = (vv[i] >= 0 && vv[i] < hot32) ? s_hot[vv[i] >> 5] : 0xFFFFFFFFu;
-#pragma unroll
-      for (int i = 0; i < STEPS; ++i) {
-        const int32_t v = vv[i];
-        if (v < 0) continue;
-        if (v < hot32) {
-          const uint32_t bit = 1u << (v & 31);
-          if (!(hb[i] & bit)) atomicOr(&s_hot[v >> 5], bit);
-        } else if (mk[i] == 0u) {
-          mark[v] = 1;
-        }
-      }
-      if (w1 < njt) {
-#pragma unroll
-        for (int i = 0; i < STEPS; ++i) vv[i] = vn[i];
-      }
-      A = B;
-      B = C;
-    }
-  }
-  __syncthreads();
-  uint32_t* __restrict__ slice = hot_new + (int64_t)blockIdx.x * hw;
-  for (int i = tid; i < hw; i += kMarkBlock) slice[i] = s_hot[i] & ~vis[i];
-}
-
 // finish(k): see the header comment.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_finish(
@@ -822,17 +561,20 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
   for (int64_t base = (int64_t)blockIdx.x * chunk; base < F; base += stride) {
     int32_t v[kResolveRV], p[kResolveRV];
     int64_t o[kResolveRV], end[kResolveRV];
+    // queue entries of the RV vertices, loaded together (indices clamped so
+    // the loads need no branch; entries past F are dropped)
 #pragma unroll
     for (int t = 0; t < kResolveRV; ++t) {
       const int64_t j = base + t * kResolveBlock + tid;
-      v[t] = -1;
+      const int64_t jc = j < F ? j : F - 1;
+      const int64_t jn = jc + 1 < F ? jc + 1 : jc;
+      const int32_t vj = qv[jc];
+      const int64_t oj = qo[jc], e0 = qe[jc], e1 = qe[jn];
+      const bool ok = j < F;
+      v[t] = ok ? vj : -1;
       p[t] = -1;
-      o[t] = end[t] = 0;
-      if (j < F) {
-        v[t] = qv[j];
-        o[t] = qo[j];
-        end[t] = o[t] + ((j + 1 < F ? qe[j + 1] : T) - qe[j]);
-      }
+      o[t] = ok ? oj : 0;
+      end[t] = ok ? oj + ((jc + 1 < F ? e1 : T) - e0) : 0;
     }
     // first kFirst adjacencies of all RV vertices together; the LDS tests of
     // hot neighbours come first, so mark bytes are read only for the cold
@@ -1037,7 +779,7 @@ int csr_alloc_workspace(bfs_graph* g) {
     g->device_bytes += std::max<int64_t>(c.nwords, 1) * 32;
     // one slice of hot-prefix bits per mark-path workgroup (one per CU)
     c.hot_words = (int)std::min<int64_t>(std::max<int64_t>(c.nwords, 1), kHotWordsMax);
-    c.hot_slices = grid_for(g->device, (const void*)k_expand_mark, kMarkBlock, 1);
+    c.hot_slices = mark_expand_grid(g->device);
     BFS_HIP(hipMalloc(&c.hot_new, (size_t)c.hot_slices * c.hot_words * 4));
     g->device_bytes += (int64_t)c.hot_slices * c.hot_words * 4;
   }
@@ -1164,7 +906,9 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   mp.symmetric = (claim != 1) && c.symmetric;
   mp.min_edges = g->opt.claim_threshold > 0 ? (long long)g->opt.claim_threshold
                                             : std::max<long long>(c.n / 64, 4096);
-  mp.min_vertices = std::max<long long>(c.n / 1024, 1024);
+  mp.min_vertices = g->opt.claim_min_frontier > 0
+                        ? (long long)g->opt.claim_min_frontier
+                        : std::min<long long>(std::max<long long>(c.n / 1024, 1024), 4096);
   if (claim == 2) mp.min_edges = mp.min_vertices = 1;
 
   int32_t* d_parent = parent;
@@ -1227,23 +971,24 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   for (;;) {
     for (int b = 0; b < batch; ++b) {
       if (prof) {
-        const size_t need = 3 * (size_t)(k + 1) + 2;
+        const size_t need = 4 * (size_t)(k + 1) + 2;
         while (g->ev.size() < need) {
           hipEvent_t ev;
           BFS_HIP(hipEventCreate(&ev));
           g->ev.push_back(ev);
         }
-        BFS_HIP(hipEventRecord(g->ev[2 + 3 * k], s));
+        BFS_HIP(hipEventRecord(g->ev[2 + 4 * k], s));
       }
       k_expand<kExpandBlock><<<ge, kExpandBlock, 0, s>>>(koff, kcol, c.vis, d_parent, d_level,
                                                          c.mark, q, c.jstart, c.njstart, c.zq,
                                                          c.state, c.cbits, mp, kinv);
+      if (prof) BFS_HIP(hipEventRecord(g->ev[3 + 4 * k], s));
       if (mp.symmetric) {
-        k_expand_mark<<<gm, kMarkBlock, 0, s>>>(kcol, c.vis, c.mark, q, c.jstart, c.njstart,
-                                                c.state, c.cbits, mp, c.hot_words, c.hot_new,
-                                                c.n, g->opt.cold_probe == 3 ? 0 : g->opt.cold_probe);
+        mark_expand_launch(gm, s, kcol, c.vis, c.mark, q, c.jstart, c.njstart, c.state, c.cbits,
+                           mp, c.hot_words, c.hot_new, c.n,
+                           g->opt.cold_probe == 3 ? 0 : g->opt.cold_probe);
       }
-      if (prof) BFS_HIP(hipEventRecord(g->ev[3 + 3 * k], s));
+      if (prof) BFS_HIP(hipEventRecord(g->ev[4 + 4 * k], s));
       k_finish<kFinishBlock><<<gf, kFinishBlock, 0, s>>>(koff, c.vis, c.mark, q, c.jstart,
                                                          c.njstart, c.zq, c.state, c.cbits,
                                                          c.n, c.nwords, mp, c.hot_words,
@@ -1251,7 +996,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
       if (mp.symmetric)
         k_resolve<<<gr, kResolveBlock, 0, s>>>(kcol, d_parent, d_level, c.mark, q, c.state,
                                                c.cbits, mp, kinv, c.hot_words);
-      if (prof) BFS_HIP(hipEventRecord(g->ev[4 + 3 * k], s));
+      if (prof) BFS_HIP(hipEventRecord(g->ev[5 + 4 * k], s));
       ++k;
     }
     BFS_HIP(hipGetLastError());
@@ -1287,12 +1032,15 @@ int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st) {
   st->expand_launches = g->expand_launches;
   st->mark_levels = h.mark_levels;
   if (g->profiled) {
-    double sum = 0.0;
+    double sum = 0.0, msum = 0.0;
     for (int k = 0; k < g->expand_launches; ++k) {
-      float ms = 0.f;
-      BFS_HIP(hipEventElapsedTime(&ms, g->ev[2 + 3 * k], g->ev[3 + 3 * k]));
+      float ms = 0.f, mm = 0.f;
+      BFS_HIP(hipEventElapsedTime(&ms, g->ev[2 + 4 * k], g->ev[4 + 4 * k]));
+      BFS_HIP(hipEventElapsedTime(&mm, g->ev[3 + 4 * k], g->ev[4 + 4 * k]));
       sum += ms;
+      msum += mm;
     }
+    st->mark_ms = msum;
     float tot = 0.f;
     BFS_HIP(hipEventElapsedTime(&tot, g->ev[0], g->ev[1]));
     st->expand_ms = sum;
@@ -1317,10 +1065,12 @@ int csr_level_info(bfs_graph* g, bfs_level_info_t* out, int32_t capacity, int32_
     L.mark = hmark[(size_t)k];
     L.frontier = (int64_t)(hist[(size_t)k] & cmask);
     L.edges = (int64_t)(hist[(size_t)k] >> g->csr.cbits);
-    float a = 0.f, b = 0.f;
-    BFS_HIP(hipEventElapsedTime(&a, g->ev[2 + 3 * i], g->ev[3 + 3 * i]));
-    BFS_HIP(hipEventElapsedTime(&b, g->ev[3 + 3 * i], g->ev[4 + 3 * i]));
+    float a = 0.f, m = 0.f, b = 0.f;
+    BFS_HIP(hipEventElapsedTime(&a, g->ev[2 + 4 * i], g->ev[4 + 4 * i]));
+    BFS_HIP(hipEventElapsedTime(&m, g->ev[3 + 4 * i], g->ev[4 + 4 * i]));
+    BFS_HIP(hipEventElapsedTime(&b, g->ev[4 + 4 * i], g->ev[5 + 4 * i]));
     L.expand_ms = a;
+    L.mark_ms = m;
     L.finish_ms = b;
   }
   *count = g->expand_launches;

@@ -1,0 +1,63 @@
+// Definitions shared by the CSR level kernels (bfs_csr.hip) and the
+// mark-and-resolve expand kernel (bfs_mark.hip): launch constants, the
+// frontier queues, the per-level choice between the two ways of claiming new
+// vertices, and the mark-byte tags.
+#pragma once
+
+#include "bfs_internal.h"
+
+namespace bfsi {
+
+// jstart granularity and claim-path tile: 1024 edges (256 threads x 4)
+constexpr int kTileJ = 1024;
+// mark path: one 1024-thread workgroup per CU, each wave on its own
+// 1024-edge tiles
+constexpr int kMarkBlock = 1024;
+// Hot prefix of the visited bitmap kept in LDS by the mark path: the first
+// 39936 * 32 vertices (156 KiB of the CU's 160 KiB; the rest holds the
+// waves' row-start masks). In a degree-ordered copy these are the
+// highest-degree vertices, the targets of most probes.
+constexpr int kHotWordsMax = 39936;
+// mark-and-resolve: vertices of degree above this search their parent with
+// the whole wave instead of one thread
+constexpr int kSerialScan = 64;
+
+// Mark bytes: 0 = not reached, 1 = touched by the current level's frontier,
+// 2 + (level mod 3) = reached at that level. A neighbour of a vertex at level
+// k lies at level k-1, k or k+1 (or is unreached), so the tag identifies
+// "one level up" exactly.
+__device__ __forceinline__ uint8_t level_tag(int k) { return (uint8_t)(2 + k % 3); }
+
+struct Queues {
+  int32_t* qv[2];
+  int64_t* qo[2];
+  int64_t* qe[2];
+};
+
+// Level selection: mark-and-resolve when the graph is symmetric and the
+// input frontier is large in both edges and vertices (a small frontier makes
+// every new vertex search far for one of its few frontier neighbours).
+struct MarkPolicy {
+  int symmetric;
+  long long min_edges;
+  long long min_vertices;
+};
+
+__device__ __forceinline__ bool mark_level(unsigned long long cin, int cbits,
+                                           const MarkPolicy& mp) {
+  const unsigned long long cmask = (1ull << cbits) - 1;
+  return mp.symmetric && (long long)(cin >> cbits) >= mp.min_edges &&
+         (long long)(cin & cmask) >= mp.min_vertices;
+}
+
+
+// Mark expand (bfs_mark.hip): workgroups to launch (one per CU, its LDS holds
+// the hot prefix of the visited bitmap) and the launch itself; probe: 0 =
+// by reached fraction, 1 = mark byte, 2 = visited word first.
+int mark_expand_grid(int device);
+void mark_expand_launch(int grid, hipStream_t s, const int32_t* col, const uint32_t* vis,
+                        uint8_t* mark, const Queues& q, const int32_t* jstart_base, int64_t njs,
+                        const LevelState* st, int cbits, const MarkPolicy& mp, int hw,
+                        uint32_t* hot_new, int64_t n, int probe);
+
+}  // namespace bfsi

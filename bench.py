@@ -212,6 +212,9 @@ def spmspv_leg(torch, graphgen, B, np):
     blk = graphgen.dcsc_block(26, 1 << 24, 4)
     log(f"share 2^26 x 2^26: nnz={blk.nnz} nzc={blk.nzc} in {time.time() - t0:.1f}s")
     Gb = B.Graph.from_dcsc(blk.nrows, blk.ncols, blk.jc, blk.cp, blk.ir, trusted=True)
+    Gb.tune()   # the polyalgorithm's switch (sort path vs accumulator), measured here
+    sort_max = Gb.get_options().spmspv_sort_max
+    log(f"spmspv sort path for frontiers up to {sort_max} entries")
     cap = blk.nnz
     oi = torch.empty(cap, dtype=torch.int32, device="cuda")
     ov = torch.empty(cap, dtype=torch.int32, device="cuda")
@@ -253,6 +256,7 @@ def spmspv_leg(torch, graphgen, B, np):
             "roofline_frac": round(frac, 4) if density >= 0.01 else None,
         }
         log(f"spmspv {density * 100:g}%: p50 {p50:.1f} us")
+    out["sort_path_max_frontier"] = sort_max
     del Gb
     return out
 

@@ -127,6 +127,10 @@ typedef struct bfs_options {
                            2 = read the visited word first, the byte only when unvisited;
                            3 = 2 once a quarter of the vertices is reached, else 1
                            (0 = keep; default 3) */
+  int32_t spmspv_sort_max; /* bfs_spmspv: frontiers of up to this many entries (at most
+                              8192) take the single-workgroup sort path when their product
+                              fits it, larger ones the sparse accumulator; -1 = never
+                              (0 = keep; default 512; bfs_tune measures it) */
 } bfs_options_t;
 
 /* ---------------------------------------------------------------- graphs */
@@ -274,10 +278,17 @@ int bfs_server_destroy(bfs_server_t* s);
 /* ---------------------------------------------------------------- tuning */
 
 /*
- * Times the expand-kernel launch shapes on this graph from a few roots and
- * keeps the fastest in the handle's options; when cache_path is not NULL
- * the choice is read from / appended to that file, keyed by device name and
- * graph shape.
+ * Autotuner. CSR graph: times BFS from its three largest-degree vertices
+ * under each combination of expand grid (2, 4, 8 workgroups per CU), levels
+ * per host check (2, 4, 8) and mark-level frontier floor (1024, 4096, 16384)
+ * and keeps the fastest in the handle's options. DCSC share: times both
+ * branches of the SpMSpV polyalgorithm (section 4.2: sparse accumulator, or
+ * the sort-based merge) on sorted random frontiers of 64 to 8192 entries and
+ * sets spmspv_sort_max to the largest size where the sort was faster (-1 if
+ * never). When cache_path is not NULL the choice is read from / appended to
+ * that text file, one line per device name and graph shape. Results of later
+ * runs do not depend on the choice, only their speed. Holds the handle's run
+ * lock while timing.
  */
 int bfs_tune(bfs_graph_t* g, const char* cache_path);
 

@@ -69,7 +69,7 @@ class Options(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32), ("lds_bitmap", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("claim", ctypes.c_int32),
                 ("claim_threshold", ctypes.c_int32), ("claim_min_frontier", ctypes.c_int32),
-                ("cold_probe", ctypes.c_int32)]
+                ("cold_probe", ctypes.c_int32), ("spmspv_sort_max", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -265,10 +265,10 @@ class Graph:
         return n.value, nnz.value, b.value
 
     def set_options(self, mode=0, batch_levels=0, grid_blocks=0, lds_bitmap=0, profile=0,
-                    claim=0, claim_threshold=0, claim_min_frontier=0, cold_probe=0):
+                    claim=0, claim_threshold=0, claim_min_frontier=0, cold_probe=0,
+                    spmspv_sort_max=0):
         o = Options(mode, batch_levels, grid_blocks, lds_bitmap, profile, claim, claim_threshold,
-                    claim_min_frontier,
-                    cold_probe)
+                    claim_min_frontier, cold_probe, spmspv_sort_max)
         _check(load().bfs_graph_set_options(self.handle, ctypes.byref(o)),
                "bfs_graph_set_options")
 

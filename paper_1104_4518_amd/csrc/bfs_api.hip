@@ -53,6 +53,7 @@ void default_options(bfs_options_t* o) {
   o->claim_threshold = 0;
   o->claim_min_frontier = 0;
   o->cold_probe = 3;
+  o->spmspv_sort_max = 512;
 }
 
 }  // namespace
@@ -235,6 +236,8 @@ int bfs_graph_set_options(bfs_graph_t* g, const bfs_options_t* opt) {
   if (opt->cold_probe < 0 || opt->cold_probe > 3)
     return fail(BFS_ERR_ARG, "cold_probe must be 1, 2 or 3");
   if (opt->cold_probe) g->opt.cold_probe = opt->cold_probe;
+  if (opt->spmspv_sort_max < -1) return fail(BFS_ERR_ARG, "spmspv_sort_max must be >= -1");
+  if (opt->spmspv_sort_max) g->opt.spmspv_sort_max = opt->spmspv_sort_max;
   if (opt->claim) g->opt.claim = opt->claim;
   if (opt->claim_threshold) g->opt.claim_threshold = opt->claim_threshold;
   if (opt->claim_min_frontier) g->opt.claim_min_frontier = opt->claim_min_frontier;

@@ -13,6 +13,7 @@
 #include <numeric>
 #include <sstream>
 #include <unordered_set>
+#include <string>
 #include <vector>
 
 #include "bfs_multi.h"
@@ -84,6 +85,127 @@ double query_cost(const bfs_graph* g) {
   double depth = (double)g->hint_depth;
   if (depth <= 0) depth = (m / std::max(n, 1.0) < 6.0) ? 2.0 * std::sqrt(n) : 16.0;
   return edges * 0.5 + depth * 4000.0;
+}
+
+// Launch shapes and the mark-level frontier floor of a CSR graph: BFS from
+// its three largest-degree vertices (among the first 2^22) under each
+// setting, the fastest kept.
+int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
+  const int64_t n = g->csr.n;
+  int32_t *parent = nullptr, *level = nullptr;
+  BFS_HIP(hipMalloc(&parent, (size_t)n * 4));
+  BFS_HIP(hipMalloc(&level, (size_t)n * 4));
+  std::vector<int64_t> off((size_t)std::min<int64_t>(n + 1, 1 << 22));
+  const int64_t probe = (int64_t)off.size() - 1;
+  BFS_HIP(hipMemcpy(off.data(), g->csr.off, off.size() * 8, hipMemcpyDeviceToHost));
+  std::vector<int32_t> cand;
+  for (int64_t v = 0; v < probe; ++v)
+    if (off[(size_t)v + 1] > off[(size_t)v]) cand.push_back((int32_t)v);
+  std::partial_sort(cand.begin(), cand.begin() + std::min<size_t>(3, cand.size()), cand.end(),
+                    [&](int32_t a, int32_t b) {
+                      return off[(size_t)a + 1] - off[(size_t)a] >
+                             off[(size_t)b + 1] - off[(size_t)b];
+                    });
+  cand.resize(std::min<size_t>(3, cand.size()));
+  if (cand.empty()) cand.push_back(0);
+  std::lock_guard<std::mutex> run_lk(g->run_mu);
+  const bfs_options_t saved = g->opt;
+  const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  double best = 1e30;
+  int best_grid = cus * 8, best_batch = 4, best_minf = 4096;
+  int rc = BFS_OK;
+  for (int per_cu : {2, 4, 8}) {
+    for (int batch : {2, 4, 8}) {
+      for (int minf : {1024, 4096, 16384}) {
+        g->opt.grid_blocks = cus * per_cu;
+        g->opt.batch_levels = batch;
+        g->opt.claim_min_frontier = minf;
+        rc = csr_run(g, cand[0], parent, level, nullptr, true);   // warm
+        if (rc != BFS_OK) break;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int32_t r : cand) {
+          rc = csr_run(g, r, parent, level, nullptr, true);
+          if (rc != BFS_OK) break;
+        }
+        const double dt =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (rc == BFS_OK && dt < best) {
+          best = dt;
+          best_grid = g->opt.grid_blocks;
+          best_batch = batch;
+          best_minf = minf;
+        }
+      }
+      if (rc != BFS_OK) break;
+    }
+    if (rc != BFS_OK) break;
+  }
+  (void)hipFree(parent);
+  (void)hipFree(level);
+  g->opt = saved;
+  if (rc != BFS_OK) return rc;
+  g->opt.grid_blocks = best_grid;
+  g->opt.batch_levels = best_batch;
+  g->opt.claim_min_frontier = best_minf;
+  std::ostringstream o;
+  o << "grid=" << best_grid << " batch=" << best_batch << " min_frontier=" << best_minf;
+  *result = o.str();
+  return BFS_OK;
+}
+
+// The SpMSpV polyalgorithm's switch for a DCSC share: for frontiers of 64 to
+// 8192 sorted random column ids, time the sort path and the accumulator; the
+// sort path is kept up to the largest size where it was faster (-1 = never).
+int tune_dcsc(bfs_graph* g, std::string* result) {
+  const DcscDev& d = g->dcsc;
+  const int sizes[] = {64, 512, 2048, 8192};
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(d.nrows, d.nnz));
+  int32_t *f = nullptr, *oi = nullptr, *ov = nullptr;
+  BFS_HIP(hipMalloc(&f, 8192 * 4));
+  BFS_HIP(hipMalloc(&oi, (size_t)cap * 4));
+  BFS_HIP(hipMalloc(&ov, (size_t)cap * 4));
+  std::lock_guard<std::mutex> run_lk(g->run_mu);
+  const bfs_options_t saved = g->opt;
+  uint64_t x = 0x9E3779B97F4A7C15ull;   // fixed seed: a repeatable choice
+  int chosen = -1;
+  int rc = BFS_OK;
+  for (int sz : sizes) {
+    const int k = (int)std::min<int64_t>(sz, d.ncols);
+    if (k <= 0) break;
+    std::vector<int32_t> h;
+    std::unordered_set<int32_t> seen;
+    while ((int)h.size() < k) {
+      x ^= x << 13;   // xorshift64
+      x ^= x >> 7;
+      x ^= x << 17;
+      const int32_t c = (int32_t)(x % (uint64_t)d.ncols);
+      if (seen.insert(c).second) h.push_back(c);
+    }
+    std::sort(h.begin(), h.end());
+    BFS_HIP(hipMemcpy(f, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+    double t[2] = {0, 0};
+    for (int path = 0; path < 2 && rc == BFS_OK; ++path) {
+      g->opt.spmspv_sort_max = path ? 8192 : -1;
+      bfs_svec_t fv{k, k, f, nullptr}, out{0, cap, oi, ov};
+      rc = dcsc_spmspv(g, &fv, &out, nullptr);   // warm
+      const auto t0 = std::chrono::steady_clock::now();
+      for (int rep = 0; rep < 5 && rc == BFS_OK; ++rep) {
+        out.nnz = 0;
+        rc = dcsc_spmspv(g, &fv, &out, nullptr);
+      }
+      t[path] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rc != BFS_OK) break;
+    if (t[1] < t[0]) chosen = k;
+  }
+  (void)hipFree(f);
+  (void)hipFree(oi);
+  (void)hipFree(ov);
+  g->opt = saved;
+  if (rc != BFS_OK) return rc;
+  g->opt.spmspv_sort_max = chosen;
+  *result = "sort_max=" + std::to_string(chosen);
+  return BFS_OK;
 }
 
 }  // namespace
@@ -176,80 +298,47 @@ int bfs_run_batch(int32_t count, bfs_graph_t* const* graphs, const int32_t* root
 }
 
 int bfs_tune(bfs_graph_t* g, const char* cache_path) {
-  if (!g || g->kind != kCsr) return fail(BFS_ERR_ARG, "bfs_tune needs a CSR graph");
+  if (!g) return fail(BFS_ERR_ARG, "NULL graph");
   try {
     hipDeviceProp_t prop;
     int dev = 0;
     (void)hipGetDevice(&dev);
     BFS_HIP(hipGetDeviceProperties(&prop, dev));
     std::ostringstream key;
-    key << prop.gcnArchName << " n=" << g->csr.n << " nnz=" << g->csr.nnz;
+    if (g->kind == kCsr)
+      key << prop.gcnArchName << " csr n=" << g->csr.n << " nnz=" << g->csr.nnz;
+    else
+      key << prop.gcnArchName << " dcsc " << g->dcsc.nrows << "x" << g->dcsc.ncols
+          << " nnz=" << g->dcsc.nnz;
     if (cache_path) {
       std::ifstream in(cache_path);
       std::string line;
       while (std::getline(in, line)) {
         const size_t bar = line.find(" | ");
         if (bar == std::string::npos || line.substr(0, bar) != key.str()) continue;
-        int grid = 0, batch = 0;
-        if (std::sscanf(line.c_str() + bar + 3, "grid=%d batch=%d", &grid, &batch) == 2 &&
-            grid > 0 && batch > 0) {
+        const char* rest = line.c_str() + bar + 3;
+        int grid = 0, batch = 0, minf = 0, sort_max = 0;
+        if (g->kind == kCsr &&
+            std::sscanf(rest, "grid=%d batch=%d min_frontier=%d", &grid, &batch, &minf) == 3 &&
+            grid > 0 && batch > 0 && minf > 0) {
           g->opt.grid_blocks = grid;
           g->opt.batch_levels = batch;
+          g->opt.claim_min_frontier = minf;
+          return BFS_OK;
+        }
+        if (g->kind == kDcsc && std::sscanf(rest, "sort_max=%d", &sort_max) == 1 &&
+            (sort_max == -1 || sort_max > 0)) {
+          g->opt.spmspv_sort_max = sort_max;
           return BFS_OK;
         }
       }
     }
-    const int64_t n = g->csr.n;
-    int32_t *parent = nullptr, *level = nullptr;
-    BFS_HIP(hipMalloc(&parent, (size_t)n * 4));
-    BFS_HIP(hipMalloc(&level, (size_t)n * 4));
-    // roots: the three largest-degree vertices
-    std::vector<int64_t> off((size_t)std::min<int64_t>(n + 1, 1 << 22));
-    const int64_t probe = (int64_t)off.size() - 1;
-    BFS_HIP(hipMemcpy(off.data(), g->csr.off, off.size() * 8, hipMemcpyDeviceToHost));
-    std::vector<int32_t> cand;
-    for (int64_t v = 0; v < probe; ++v)
-      if (off[(size_t)v + 1] > off[(size_t)v]) cand.push_back((int32_t)v);
-    std::partial_sort(cand.begin(), cand.begin() + std::min<size_t>(3, cand.size()), cand.end(),
-                      [&](int32_t a, int32_t b) {
-                        return off[(size_t)a + 1] - off[(size_t)a] >
-                               off[(size_t)b + 1] - off[(size_t)b];
-                      });
-    cand.resize(std::min<size_t>(3, cand.size()));
-    if (cand.empty()) cand.push_back(0);
-    std::lock_guard<std::mutex> run_lk(g->run_mu);
-    const bfs_options_t saved = g->opt;
-    const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    double best = 1e30;
-    int best_grid = saved.grid_blocks, best_batch = saved.batch_levels;
-    for (int per_cu : {2, 4, 6, 8}) {
-      for (int batch : {2, 4, 8}) {
-        g->opt.grid_blocks = cus * per_cu;
-        g->opt.batch_levels = batch;
-        int rc = csr_run(g, cand[0], parent, level, nullptr, true);   // warm
-        if (rc != BFS_OK) break;
-        const auto t0 = std::chrono::steady_clock::now();
-        for (int32_t r : cand) {
-          rc = csr_run(g, r, parent, level, nullptr, true);
-          if (rc != BFS_OK) break;
-        }
-        const double dt =
-            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (rc == BFS_OK && dt < best) {
-          best = dt;
-          best_grid = g->opt.grid_blocks;
-          best_batch = batch;
-        }
-      }
-    }
-    (void)hipFree(parent);
-    (void)hipFree(level);
-    g->opt = saved;
-    g->opt.grid_blocks = best_grid;
-    g->opt.batch_levels = best_batch;
+    std::string result;
+    const int rc = g->kind == kCsr ? tune_csr(g, prop, &result) : tune_dcsc(g, &result);
+    if (rc != BFS_OK) return rc;
     if (cache_path) {
       std::ofstream out(cache_path, std::ios::app);
-      out << key.str() << " | grid=" << best_grid << " batch=" << best_batch << "\n";
+      out << key.str() << " | " << result << "\n";
     }
     return BFS_OK;
   } catch (...) {

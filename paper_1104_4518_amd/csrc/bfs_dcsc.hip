@@ -15,6 +15,12 @@
 //   expand   rows IR[CP[p] .. CP[p+1]) of each found column
 //   combine  atomicMin into the SPA value, atomicOr into the occupied bits
 //   emit     bitmap scan -> ascending (row, value), SPA reset
+//
+// Very sparse frontiers take the other branch of the paper's polyalgorithm
+// (section 4.2: a SPA for denser products, a sort-based merge when the
+// product is small): one workgroup looks up the columns, writes the
+// products as packed (row, value) keys into LDS, sorts them (bitonic) and
+// keeps the first key of each row, so no work is proportional to nrows.
 #include "bfs_internal.h"
 
 #include <algorithm>
@@ -191,6 +197,183 @@ __global__ __launch_bounds__(kEmitBlock) void k_spa_emit(
   }
 }
 
+// Sort path: frontier entries and products it can hold in LDS.
+constexpr int kSortBlock = 1024;
+constexpr int kSortMaxF = 8192;
+constexpr int kSortMaxP = 8192;
+
+__device__ __forceinline__ int32_t dcsc_lookup(int32_t k, const int32_t* __restrict__ jc,
+                                               const int32_t* __restrict__ aux, int shift) {
+  const int64_t b = (int64_t)k >> shift;
+  int32_t lo = aux[b], hi = aux[b + 1];
+  const int32_t end = hi;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (jc[mid] < k) lo = mid + 1; else hi = mid;
+  }
+  return (lo < end && jc[lo] == k) ? lo : -1;
+}
+
+// Block-wide exclusive scan of one int per thread (kSortBlock threads).
+__device__ __forceinline__ int sort_block_scan(int v, int* s_w, int& total) {
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  if (lane == 63) s_w[wid] = incl;
+  __syncthreads();
+  int base = 0;
+  total = 0;
+  for (int x = 0; x < kSortBlock / 64; ++x) {
+    if (x < wid) base += s_w[x];
+    total += s_w[x];
+  }
+  __syncthreads();
+  return base + incl - v;
+}
+
+// counters[0] = output count, [1] = frontier error, [2] = product too large
+// for LDS (the caller then runs the SPA path).
+__global__ __launch_bounds__(kSortBlock) void k_spmspv_sort(
+    int64_t fnnz, const int32_t* __restrict__ fidx, const int32_t* __restrict__ fval,
+    int32_t ncols, const int32_t* __restrict__ jc, const int32_t* __restrict__ cp,
+    const int32_t* __restrict__ ir, const int32_t* __restrict__ aux, int shift,
+    unsigned long long* __restrict__ counters, int64_t capacity, int32_t* __restrict__ out_idx,
+    int32_t* __restrict__ out_val) {
+  __shared__ unsigned long long s_key[kSortMaxP];
+  __shared__ int s_w[kSortBlock / 64];
+  __shared__ int s_err;
+  const int tid = threadIdx.x;
+  constexpr int PER = kSortMaxF / kSortBlock;
+  if (tid == 0) s_err = 0;
+  __syncthreads();
+  // lookup: thread t owns entries t*PER .. t*PER+PER-1 (contiguous, so the
+  // product slots come out in frontier order); the PER lookups advance
+  // together, one load each per step
+  int32_t kk[PER], lo[PER], hi[PER], bend[PER];
+  {
+    const int64_t i0 = (int64_t)tid * PER;
+    const int32_t prev = (i0 > 0 && i0 <= fnnz) ? fidx[i0 - 1] : -1;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) kk[j] = (i0 + j < fnnz) ? fidx[i0 + j] : -1;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (i0 + j >= fnnz) continue;
+      const int32_t before = j ? kk[j - 1] : prev;
+      if (kk[j] < 0 || kk[j] >= ncols || (i0 + j > 0 && before >= kk[j])) bad = true;
+    }
+    if (bad) s_err = 1;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      lo[j] = hi[j] = bend[j] = 0;
+      if (i0 + j < fnnz && kk[j] >= 0 && kk[j] < ncols) {
+        const int64_t bk = (int64_t)kk[j] >> shift;
+        lo[j] = aux[bk];
+        hi[j] = bend[j] = aux[bk + 1];
+      }
+    }
+    for (;;) {
+      bool any = false;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        if (lo[j] < hi[j]) {
+          const int32_t mid = (lo[j] + hi[j]) >> 1;
+          if (jc[mid] < kk[j]) lo[j] = mid + 1; else hi[j] = mid;
+          any = true;
+        }
+      }
+      if (!any) break;
+    }
+  }
+  int32_t q0[PER], len[PER];
+  int mine = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t i = (int64_t)tid * PER + j;
+    const bool found = i < fnnz && lo[j] < bend[j] && jc[lo[j]] == kk[j];
+    q0[j] = found ? cp[lo[j]] : 0;
+    len[j] = found ? cp[lo[j] + 1] - q0[j] : 0;
+    mine += len[j];
+  }
+  __syncthreads();   // s_err complete
+  int total = 0;
+  int off = sort_block_scan(mine, s_w, total);
+  if (s_err || total > kSortMaxP) {
+    if (tid == 0) {
+      if (s_err) counters[1] = 1ull;
+      else counters[2] = 1ull;
+    }
+    return;
+  }
+  // expand: products as (row << 32) | order-preserving value; the first
+  // product of every entry is loaded together
+  {
+    int32_t r0[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) r0[j] = len[j] > 0 ? ir[q0[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int64_t i = (int64_t)tid * PER + j;
+      if (len[j] == 0) continue;
+      const uint32_t key = (uint32_t)(fval ? fval[i] : kk[j]) ^ 0x80000000u;
+      s_key[off] = ((unsigned long long)(uint32_t)r0[j] << 32) | key;
+      for (int32_t q = 1; q < len[j]; ++q)
+        s_key[off + q] = ((unsigned long long)(uint32_t)ir[q0[j] + q] << 32) | key;
+      off += len[j];
+    }
+  }
+  // pad to a power of two with keys above every product
+  int np2 = 1;
+  while (np2 < total) np2 <<= 1;
+  for (int i = total + tid; i < np2; i += kSortBlock) s_key[i] = ~0ull;
+  __syncthreads();
+  // bitonic sort, ascending
+  for (int size = 2; size <= np2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < (np2 >> 1); i += kSortBlock) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const unsigned long long a = s_key[lo], b = s_key[hi];
+        if ((a > b) == up) {
+          s_key[lo] = b;
+          s_key[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // first key of each row = its minimum value; rows come out ascending
+  constexpr int PP = kSortMaxP / kSortBlock;
+  int keep[PP];
+  int cnt = 0;
+#pragma unroll
+  for (int j = 0; j < PP; ++j) {
+    const int i = tid * PP + j;
+    keep[j] = (i < total && (i == 0 || (s_key[i] >> 32) != (s_key[i - 1] >> 32))) ? 1 : 0;
+    cnt += keep[j];
+  }
+  int nout = 0;
+  int pos = sort_block_scan(cnt, s_w, nout);
+  const bool write = nout <= capacity;
+#pragma unroll
+  for (int j = 0; j < PP; ++j) {
+    const int i = tid * PP + j;
+    if (keep[j]) {
+      if (write) {
+        out_idx[pos] = (int32_t)(s_key[i] >> 32);
+        out_val[pos] = (int32_t)((uint32_t)s_key[i] ^ 0x80000000u);
+      }
+      ++pos;
+    }
+  }
+  if (tid == 0) counters[0] = (unsigned long long)nout;
+}
+
 }  // namespace
 
 int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
@@ -228,9 +411,9 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   BFS_HIP(hipMemsetAsync(d.spa_occ, 0, (size_t)std::max<int64_t>(d.nwords, 1) * 4, s));
   d.nblk = (d.nwords + kWordsPerBlock - 1) / kWordsPerBlock;
   BFS_HIP(hipMalloc(&d.blk_count, (size_t)std::max<int64_t>(d.nblk, 1) * 8));
-  BFS_HIP(hipMalloc(&d.counters, 2 * sizeof(unsigned long long)));
-  BFS_HIP(hipMemsetAsync(d.counters, 0, 2 * sizeof(unsigned long long), s));
-  BFS_HIP(hipHostMalloc(&d.h_counters, 2 * sizeof(unsigned long long), hipHostMallocDefault));
+  BFS_HIP(hipMalloc(&d.counters, 3 * sizeof(unsigned long long)));
+  BFS_HIP(hipMemsetAsync(d.counters, 0, 3 * sizeof(unsigned long long), s));
+  BFS_HIP(hipHostMalloc(&d.h_counters, 3 * sizeof(unsigned long long), hipHostMallocDefault));
   BFS_HIP(hipStreamSynchronize(s));
   g->device_bytes += d.naux * 4 + (int64_t)std::max(d.nrows, 1) * 4 +
                      std::max<int64_t>(d.nwords, 1) * 4 + std::max<int64_t>(d.nblk, 1) * 8 + 16;
@@ -257,7 +440,29 @@ int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t 
   if (f->nnz > (int64_t)d.ncols) return fail(BFS_ERR_ARG, "frontier longer than ncols");
   if (out->capacity < 0 || (out->capacity > 0 && (!out->idx || !out->val)))
     return fail(BFS_ERR_ARG, "bad output vector");
-  BFS_HIP(hipMemsetAsync(d.counters, 0, 2 * sizeof(unsigned long long), s));
+  BFS_HIP(hipMemsetAsync(d.counters, 0, 3 * sizeof(unsigned long long), s));
+  // sort path for small frontiers (a product too large for LDS falls back)
+  const int64_t sort_max = std::min<int64_t>(g->opt.spmspv_sort_max, kSortMaxF);
+  if (f->nnz > 0 && f->nnz <= sort_max) {
+    k_spmspv_sort<<<1, kSortBlock, 0, s>>>(f->nnz, f->idx, f->val, d.ncols, d.jc, d.cp, d.ir,
+                                           d.aux, d.aux_shift, d.counters, out->capacity,
+                                           out->idx, out->val);
+    BFS_HIP(hipGetLastError());
+    BFS_HIP(hipMemcpyAsync(d.h_counters, d.counters, 3 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s));
+    BFS_HIP(hipStreamSynchronize(s));
+    if (!d.h_counters[2]) {
+      const int64_t cnt = (int64_t)d.h_counters[0];
+      if (d.h_counters[1]) {
+        out->nnz = 0;
+        return fail(BFS_ERR_ARG, "frontier indices must be strictly ascending and in [0, ncols)");
+      }
+      out->nnz = cnt;
+      if (cnt > out->capacity) return fail(BFS_ERR_CAPACITY, "output capacity too small");
+      return BFS_OK;
+    }
+    BFS_HIP(hipMemsetAsync(d.counters, 0, 3 * sizeof(unsigned long long), s));
+  }
   if (f->nnz > 0) {
     const int blk = 256;
     const int64_t grid = std::min<int64_t>((f->nnz + blk - 1) / blk, 65536);

@@ -15,8 +15,16 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fig3_dcsc.json")
 
 
-def block_on_device(b):
-    return B.Graph.from_dcsc(b.nrows, b.ncols, b.jc, b.cp, b.ir)
+def block_on_device(b, sort_max=0):
+    Gb = B.Graph.from_dcsc(b.nrows, b.ncols, b.jc, b.cp, b.ir)
+    if sort_max:
+        Gb.set_options(spmspv_sort_max=sort_max)
+    return Gb
+
+
+# both branches of the polyalgorithm: -1 = sparse accumulator only,
+# 8192 = the sort path for frontiers up to 8192 entries
+PATHS = pytest.mark.parametrize("path", [-1, 8192], ids=["spa", "sort"])
 
 
 def check(Gb, blk, fidx, fval=None):
@@ -41,13 +49,14 @@ def test_fig3_worked_example():
         assert gv.tolist() == case["out_val"]
 
 
+@PATHS
 @pytest.mark.parametrize("seed", range(6))
-def test_random_small_blocks(seed):
+def test_random_small_blocks(seed, path):
     rng = np.random.default_rng(seed)
     nr, nc = int(rng.integers(1, 3000)), int(rng.integers(1, 3000))
     a = rng.random((nr, nc)) < float(rng.choice([0.0005, 0.003, 0.02]))
     blk = graphgen.dcsc_from_dense(a)
-    Gb = block_on_device(blk)
+    Gb = block_on_device(blk, path)
     for rep in range(3):
         k = int(rng.integers(0, nc + 1))
         f = np.sort(rng.choice(nc, size=k, replace=False)).astype(np.int32)
@@ -56,11 +65,12 @@ def test_random_small_blocks(seed):
         check(Gb, blk, f, fv)
 
 
-def test_edge_cases_and_errors():
+@PATHS
+def test_edge_cases_and_errors(path):
     a = np.zeros((70, 90), dtype=bool)
     a[3, 5] = a[60, 5] = a[7, 89] = a[0, 40] = True
     blk = graphgen.dcsc_from_dense(a)
-    Gb = block_on_device(blk)
+    Gb = block_on_device(blk, path)
     say("empty frontier")
     assert check(Gb, blk, np.zeros(0, np.int32)).size == 0
     say("only empty columns")
@@ -83,10 +93,11 @@ def test_edge_cases_and_errors():
     check(Gb, blk, np.arange(90, dtype=np.int32))
 
 
-def test_empty_block():
+@PATHS
+def test_empty_block(path):
     blk = graphgen.DCSCBlock(10, 10, np.zeros(0, np.int32), np.zeros(1, np.int32),
                              np.zeros(0, np.int32))
-    Gb = block_on_device(blk)
+    Gb = block_on_device(blk, path)
     assert check(Gb, blk, np.array([1, 2], np.int32)).size == 0
 
 
@@ -102,10 +113,11 @@ def test_bad_dcsc_rejected():
     assert ei.value.code == B.BFS_ERR_FORMAT
 
 
+@PATHS
 @pytest.mark.parametrize("density", [0.0001, 0.001, 0.01, 0.1])
-def test_generated_block_scale20(density):
+def test_generated_block_scale20(density, path):
     blk = graphgen.dcsc_block(20, 1 << 18, 12)
-    Gb = block_on_device(blk)
+    Gb = block_on_device(blk, path)
     k = int(density * (1 << 20))
     for s in range(2):
         f = graphgen.frontier_sample(20, k, 300 + s)
@@ -124,3 +136,28 @@ def test_config_share_2pow26():
         say(f"share 2^26 density {density}")
         out = check(Gb, blk, f)
         assert out.size > 0
+
+
+def test_sort_path_limits_and_fallback():
+    """Frontiers of 8192 entries (the sort path's limit) and 8193 (the
+    accumulator), a product above 8192 pairs from a small frontier (the sort
+    path hands over to the accumulator), min over many candidates per row, and
+    calls alternating between the two paths on one handle."""
+    rng = np.random.default_rng(9)
+    a = rng.random((400, 20000)) < 0.002
+    blk = graphgen.dcsc_from_dense(a)
+    Gb = block_on_device(blk)
+    for k in (8192, 8193, 1, 0):
+        f = np.sort(rng.choice(20000, size=k, replace=False)).astype(np.int32)
+        say(f"sort limit frontier {k}")
+        check(Gb, blk, f)
+    dense = np.zeros((3000, 64), dtype=bool)
+    dense[:, :] = rng.random((3000, 64)) < 0.9   # ~172K products from 64 columns
+    bd = graphgen.dcsc_from_dense(dense)
+    Gd = block_on_device(bd)
+    for rep in range(3):
+        f = np.sort(rng.choice(64, size=int(rng.integers(8, 64)), replace=False)).astype(np.int32)
+        fv = rng.integers(-1000, 1000, size=f.size).astype(np.int32)
+        say(f"fallback product rep {rep}")
+        check(Gd, bd, f, fv)
+        check(Gd, bd, f[:2])

@@ -110,7 +110,11 @@ typedef struct bfs_run_stats {
 
 /* Run-time tuning knobs of a graph handle (0 = keep the current value). */
 typedef struct bfs_options {
-  int32_t mode;         /* 1 = one launch pair per level, 2 = persistent (one launch) */
+  int32_t mode;         /* 1 = the level kernels enqueued level by level (batch_levels
+                           between host reads of the frontier size); 2 = graph mode: 16
+                           levels captured once in a hipGraph and replayed, 1, 2, 4 then
+                           8 replays between host reads (high-diameter graphs); profiling
+                           then records the whole-run time only */
   int32_t batch_levels; /* levels enqueued between host checks in mode 1 */
   int32_t grid_blocks;  /* blocks of the expand kernel */
   int32_t lds_bitmap;   /* 1 = stage the visited bitmap in LDS when it fits */
@@ -179,10 +183,10 @@ int bfs_graph_get_options(const bfs_graph_t* g, bfs_options_t* opt);
 int bfs_run(bfs_graph_t* g, int32_t root, int32_t* parent, int32_t* level);
 
 /*
- * Same as bfs_run on `hip_stream`. In mode 2 (persistent) and for device
- * outputs it enqueues work only and returns at once; in mode 1 it waits for
- * level counts between batches of levels. Device errors are reported by the
- * next synchronising call on the handle.
+ * Same as bfs_run on `hip_stream`. The host still reads the frontier size
+ * between batches of levels (so the call returns once the last level is
+ * enqueued); with device outputs it does not wait for the final copies.
+ * Device errors are reported by the next synchronising call on the handle.
  */
 int bfs_run_async(bfs_graph_t* g, int32_t root, int32_t* parent, int32_t* level,
                   void* hip_stream);

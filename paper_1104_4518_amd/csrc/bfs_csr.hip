@@ -42,6 +42,7 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <cstring>
 #include <vector>
 
 namespace bfsi {
@@ -756,6 +757,8 @@ __global__ void k_widen_offsets(int64_t n1, const int32_t* __restrict__ src,
 
 constexpr int kExpandBlock = 256;
 constexpr int kFinishBlock = 256;
+// graph mode: levels per captured graph
+constexpr int kGraphLevels = 16;
 
 }  // namespace
 
@@ -803,6 +806,8 @@ void csr_free(bfs_graph* g) {
   (void)hipFree(c.mark);
   (void)hipFree(c.hot_new);
   (void)hipFree(c.state);
+  if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
+  if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
   (void)hipFree(c.tmp_parent);
   (void)hipFree(c.tmp_level);
   (void)hipFree(c.roff);
@@ -966,45 +971,104 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   const int batch = g->opt.batch_levels > 0 ? g->opt.batch_levels : 4;
   const unsigned long long cmask = (1ull << c.cbits) - 1;
   const bool prof = g->opt.profile > 0;
-  g->profiled = prof ? 1 : 0;
+  const int probe = g->opt.cold_probe == 3 ? 0 : g->opt.cold_probe;
+  // One level: its (up to) four launches; ev_base >= 0 brackets them with
+  // events ev_base .. ev_base + 3 (claim expand, mark expand, finish+resolve).
+  auto enqueue_level = [&](hipStream_t st, int64_t ev_base) -> int {
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base], st));
+    k_expand<kExpandBlock><<<ge, kExpandBlock, 0, st>>>(koff, kcol, c.vis, d_parent, d_level,
+                                                        c.mark, q, c.jstart, c.njstart, c.zq,
+                                                        c.state, c.cbits, mp, kinv);
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 1], st));
+    if (mp.symmetric)
+      mark_expand_launch(gm, st, kcol, c.vis, c.mark, q, c.jstart, c.njstart, c.state, c.cbits,
+                         mp, c.hot_words, c.hot_new, c.n, probe);
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 2], st));
+    k_finish<kFinishBlock><<<gf, kFinishBlock, 0, st>>>(koff, c.vis, c.mark, q, c.jstart,
+                                                        c.njstart, c.zq, c.state, c.cbits, c.n,
+                                                        c.nwords, mp, c.hot_words, c.hot_new,
+                                                        gm);
+    if (mp.symmetric)
+      k_resolve<<<gr, kResolveBlock, 0, st>>>(kcol, d_parent, d_level, c.mark, q, c.state,
+                                              c.cbits, mp, kinv, c.hot_words);
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
+    return BFS_OK;
+  };
   int64_t k = 0;
-  for (;;) {
-    for (int b = 0; b < batch; ++b) {
-      if (prof) {
-        const size_t need = 4 * (size_t)(k + 1) + 2;
-        while (g->ev.size() < need) {
-          hipEvent_t ev;
-          BFS_HIP(hipEventCreate(&ev));
-          g->ev.push_back(ev);
-        }
-        BFS_HIP(hipEventRecord(g->ev[2 + 4 * k], s));
+  if (g->opt.mode == 2) {
+    // Graph mode: kGraphLevels levels captured once per (outputs, policy,
+    // launch shapes) and replayed until a level finds an empty frontier;
+    // replays between host checks double up to 8.
+    GraphKey key{};
+    key.parent = d_parent;
+    key.level = d_level;
+    key.mp_sym = mp.symmetric;
+    key.mp_edges = mp.min_edges;
+    key.mp_vertices = mp.min_vertices;
+    key.probe = probe;
+    key.grids[0] = ge;
+    key.grids[1] = gm;
+    key.grids[2] = gf;
+    key.grids[3] = gr;
+    if (!c.gexec || std::memcmp(&key, &c.gkey, sizeof(key)) != 0) {
+      if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
+      c.gexec = nullptr;
+      if (!c.cap_stream) BFS_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+      BFS_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc = BFS_OK;
+      for (int l = 0; l < kGraphLevels && rc == BFS_OK; ++l) rc = enqueue_level(c.cap_stream, -1);
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(c.cap_stream, &graph);
+      if (rc != BFS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
       }
-      k_expand<kExpandBlock><<<ge, kExpandBlock, 0, s>>>(koff, kcol, c.vis, d_parent, d_level,
-                                                         c.mark, q, c.jstart, c.njstart, c.zq,
-                                                         c.state, c.cbits, mp, kinv);
-      if (prof) BFS_HIP(hipEventRecord(g->ev[3 + 4 * k], s));
-      if (mp.symmetric) {
-        mark_expand_launch(gm, s, kcol, c.vis, c.mark, q, c.jstart, c.njstart, c.state, c.cbits,
-                           mp, c.hot_words, c.hot_new, c.n,
-                           g->opt.cold_probe == 3 ? 0 : g->opt.cold_probe);
+      if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+      const hipError_t ei = hipGraphInstantiate(&c.gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        c.gexec = nullptr;
+        return hip_fail(ei, "hipGraphInstantiate");
       }
-      if (prof) BFS_HIP(hipEventRecord(g->ev[4 + 4 * k], s));
-      k_finish<kFinishBlock><<<gf, kFinishBlock, 0, s>>>(koff, c.vis, c.mark, q, c.jstart,
-                                                         c.njstart, c.zq, c.state, c.cbits,
-                                                         c.n, c.nwords, mp, c.hot_words,
-                                                         c.hot_new, gm);
-      if (mp.symmetric)
-        k_resolve<<<gr, kResolveBlock, 0, s>>>(kcol, d_parent, d_level, c.mark, q, c.state,
-                                               c.cbits, mp, kinv, c.hot_words);
-      if (prof) BFS_HIP(hipEventRecord(g->ev[5 + 4 * k], s));
-      ++k;
+      c.gkey = key;
     }
-    BFS_HIP(hipGetLastError());
-    BFS_HIP(hipMemcpyAsync(g->h_ctr, &c.state->ctr[k % 3], sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, s));
-    BFS_HIP(hipStreamSynchronize(s));
-    if ((*g->h_ctr & cmask) == 0) break;
-    if (k > c.n + 2) return fail(BFS_ERR_DEVICE, "level loop did not terminate");
+    int replays = 1;
+    for (;;) {
+      for (int r = 0; r < replays; ++r) {
+        BFS_HIP(hipGraphLaunch(c.gexec, s));
+        k += kGraphLevels;
+      }
+      BFS_HIP(hipMemcpyAsync(g->h_ctr, &c.state->ctr[k % 3], sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s));
+      BFS_HIP(hipStreamSynchronize(s));
+      if ((*g->h_ctr & cmask) == 0) break;
+      if (k > c.n + 2) return fail(BFS_ERR_DEVICE, "level loop did not terminate");
+      replays = std::min(replays * 2, 8);
+    }
+    g->profiled = prof ? 2 : 0;   // whole-run time only
+  } else {
+    g->profiled = prof ? 1 : 0;
+    for (;;) {
+      for (int b = 0; b < batch; ++b) {
+        if (prof) {
+          const size_t need = 4 * (size_t)(k + 1) + 2;
+          while (g->ev.size() < need) {
+            hipEvent_t ev;
+            BFS_HIP(hipEventCreate(&ev));
+            g->ev.push_back(ev);
+          }
+        }
+        const int rc = enqueue_level(s, prof ? 2 + 4 * k : -1);
+        if (rc != BFS_OK) return rc;
+        ++k;
+      }
+      BFS_HIP(hipGetLastError());
+      BFS_HIP(hipMemcpyAsync(g->h_ctr, &c.state->ctr[k % 3], sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s));
+      BFS_HIP(hipStreamSynchronize(s));
+      if ((*g->h_ctr & cmask) == 0) break;
+      if (k > c.n + 2) return fail(BFS_ERR_DEVICE, "level loop did not terminate");
+    }
   }
   g->expand_launches = (int)k;
   if (prof) BFS_HIP(hipEventRecord(g->ev[1], s));
@@ -1031,7 +1095,7 @@ int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st) {
   st->frontier_total = (int64_t)h.frontier_total;
   st->expand_launches = g->expand_launches;
   st->mark_levels = h.mark_levels;
-  if (g->profiled) {
+  if (g->profiled == 1) {
     double sum = 0.0, msum = 0.0;
     for (int k = 0; k < g->expand_launches; ++k) {
       float ms = 0.f, mm = 0.f;
@@ -1041,9 +1105,11 @@ int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st) {
       msum += mm;
     }
     st->mark_ms = msum;
+    st->expand_ms = sum;
+  }
+  if (g->profiled) {
     float tot = 0.f;
     BFS_HIP(hipEventElapsedTime(&tot, g->ev[0], g->ev[1]));
-    st->expand_ms = sum;
     st->total_ms = tot;
   }
   return BFS_OK;
@@ -1066,9 +1132,11 @@ int csr_level_info(bfs_graph* g, bfs_level_info_t* out, int32_t capacity, int32_
     L.frontier = (int64_t)(hist[(size_t)k] & cmask);
     L.edges = (int64_t)(hist[(size_t)k] >> g->csr.cbits);
     float a = 0.f, m = 0.f, b = 0.f;
-    BFS_HIP(hipEventElapsedTime(&a, g->ev[2 + 4 * i], g->ev[4 + 4 * i]));
-    BFS_HIP(hipEventElapsedTime(&m, g->ev[3 + 4 * i], g->ev[4 + 4 * i]));
-    BFS_HIP(hipEventElapsedTime(&b, g->ev[4 + 4 * i], g->ev[5 + 4 * i]));
+    if (g->profiled == 1) {   // per-level events exist (not in graph mode)
+      BFS_HIP(hipEventElapsedTime(&a, g->ev[2 + 4 * i], g->ev[4 + 4 * i]));
+      BFS_HIP(hipEventElapsedTime(&m, g->ev[3 + 4 * i], g->ev[4 + 4 * i]));
+      BFS_HIP(hipEventElapsedTime(&b, g->ev[4 + 4 * i], g->ev[5 + 4 * i]));
+    }
     L.expand_ms = a;
     L.mark_ms = m;
     L.finish_ms = b;

@@ -58,6 +58,15 @@ struct LevelState {
 };
 constexpr int kLevelHist = 4096;
 
+// What a captured level graph depends on besides the handle's own buffers.
+struct GraphKey {
+  const void* parent;
+  const void* level;
+  long long mp_edges, mp_vertices;
+  int mp_sym, probe;
+  int grids[4];
+};
+
 struct CsrDev {
   int64_t n = 0, nnz = 0;
   int cbits = 0;                 // bits of the packed counter holding the count
@@ -92,6 +101,10 @@ struct CsrDev {
   int32_t* rcol = nullptr;       // nnz, new ids
   int32_t* rank = nullptr;       // original id -> new id
   int32_t* inv = nullptr;        // new id -> original id
+  // graph mode (options.mode = 2): the captured level graph and its key
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  GraphKey gkey{};
 };
 
 struct DcscDev {

@@ -272,3 +272,42 @@ def test_degree_ordered_copy_gives_identical_results():
     for r in (0, 12345, n - 1):
         say(f"relabel directed root {r}")
         assert_bfs_equal(gd, Gd, r)
+
+
+def test_graph_mode_replays_match_oracle():
+    """Graph mode (levels captured once in a hipGraph, replayed until the
+    frontier is empty): every replay equals the oracle, with eager work and
+    synchronisation between runs, new output buffers (a new capture), host
+    outputs, a directed graph, both level-resolution ways and a grid deep
+    enough for many replays; switching back to level-by-level mode agrees."""
+    torch = torch_cuda()
+    cases = [("rmat12", graphgen.rmat_csr(12, 16, 1)), ("grid128", graphgen.grid_csr(128)),
+             ("rmat16", graphgen.rmat_csr(16, 16, 22))]
+    rng = np.random.default_rng(3)
+    n = 3000
+    src, dst = rng.integers(0, n, 20000), rng.integers(0, n, 20000)
+    order = np.lexsort((dst, src))
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(np.bincount(src[order], minlength=n))
+    cases.append(("directed", graphgen.CSR(n, off, dst[order].astype(np.int32))))
+    for name, g in cases:
+        G = graph_on_device(g)
+        G.set_options(mode=2)
+        roots = graphgen.roots(g, 3, 12)
+        for claim in (3, 1):
+            G.set_options(claim=claim)
+            for rep in range(2):
+                for r in roots:
+                    say(f"graph mode {name} claim {claim} rep {rep} root {r}")
+                    assert_bfs_equal(g, G, int(r))
+                    # eager work between replays
+                    torch.ones(1024, device="cuda").sum().item()
+        p = np.empty(g.n, np.int32)
+        lv = np.empty(g.n, np.int32)
+        say(f"graph mode {name} host outputs")
+        G.run(int(roots[0]), p, lv)
+        op, ol = oracle.bfs_graph(g, int(roots[0]))
+        assert np.array_equal(p, op) and np.array_equal(lv, ol)
+        G.set_options(mode=1)
+        say(f"level mode {name} after graph mode")
+        assert_bfs_equal(g, G, int(roots[1]))

@@ -303,3 +303,34 @@ def config_graph(name: str) -> CSR:
 def config_roots(name: str, g: CSR) -> np.ndarray:
     c = CONFIGS[name]
     return roots(g, c["roots"], c["root_seed"])
+
+
+def csr_to_2d(g: CSR, pr: int, pc: int):
+    """The p_r x p_c decomposition of a graph's adjacency matrix into DCSC
+    shares (storage only). A(v, u) = 1 for each stored adjacency u -> v, so
+    column u of the matrix holds u's adjacencies. Row block i covers global
+    rows [i*R, min((i+1)*R, n)) with R = ceil(n / p_r), column block j global
+    columns [j*C, ...) with C = ceil(n / p_c); share (i, j) is returned at
+    index i * p_c + j with local ids (rows ascending within each column).
+    Returns (R, C, shares)."""
+    n = g.n
+    R, C = -(-n // pr), -(-n // pc)
+    if (pr - 1) * R >= n or (pc - 1) * C >= n:
+        raise ValueError("every share needs at least one row and one column")
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.off))
+    dst = g.col.astype(np.int64)
+    bi, bj = dst // R, src // C
+    shares = []
+    for i in range(pr):
+        nrows = min(R, n - i * R)
+        for j in range(pc):
+            ncols = min(C, n - j * C)
+            sel = (bi == i) & (bj == j)
+            r = (dst[sel] - i * R).astype(np.int64)
+            k = (src[sel] - j * C).astype(np.int64)
+            order = np.lexsort((r, k))
+            r, k = r[order], k[order]
+            jc, start = np.unique(k, return_index=True)
+            cp = np.append(start, r.size).astype(np.int32)
+            shares.append(DCSCBlock(nrows, ncols, jc.astype(np.int32), cp, r.astype(np.int32)))
+    return R, C, shares

@@ -227,6 +227,30 @@ int bfs_last_level_info(bfs_graph_t* g, bfs_level_info_t* out, int32_t capacity,
 int bfs_spmspv(bfs_graph_t* block, const bfs_svec_t* frontier, bfs_svec_t* out,
                void* hip_stream);
 
+/*
+ * BFS over a p_r x p_c grid of DCSC shares on one GPU: the 2D-partitioned
+ * algorithm (Algorithm 3, section 3.2) with every share resident on the
+ * device and its collectives replaced by device gathers. Per level the
+ * sorted frontier is split by column block, bfs_spmspv runs on each share
+ * (the frontier entries carry their global ids as values), the products of
+ * a row block are folded with min into the rows not yet reached, and those
+ * rows become the next frontier in ascending order.
+ * shares[i * pc + j] is block (i, j) of the n x n adjacency matrix with
+ * A(v, u) = 1 for each adjacency u -> v, in local ids: row block i covers
+ * global rows [i*R, min((i+1)*R, n)) with R = ceil(n / pr), column block j
+ * global columns
+ * [j*C, min((j+1)*C, n)), C = ceil(n / pc). Every share must have that
+ * shape (at least one row and column) and the handles must be distinct
+ * (BFS_ERR_ARG otherwise). parent and level (nullable) are device arrays of
+ * n entries, caller-owned, with bfs_run's meaning: parent = minimum-id
+ * neighbour one level up. The shares' run locks are held for the call;
+ * their workspace (the SpMSpV accumulators) is used. Synchronous on
+ * `hip_stream` (the frontier size is read back every level); the call
+ * allocates its own per-run workspace (about 17 n bytes).
+ */
+int bfs_run_2d(bfs_graph_t* const* shares, int32_t pr, int32_t pc, int64_t n, int32_t root,
+               int32_t* parent, int32_t* level, void* hip_stream);
+
 /* ---------------------------------------------------------------- batches */
 
 /*

@@ -142,3 +142,38 @@ def check_bfs(g, root: int, parent, level):
     rc = lib.oracle_check_bfs(g.n, _ptr(off, _i64p), _ptr(col, _i32p), int(root),
                               _ptr(parent, _i32p), _ptr(level, _i32p), ctypes.byref(bad))
     return int(rc), int(bad.value)
+
+
+def bfs_2d(n: int, R: int, C: int, pr: int, pc: int, shares, root: int):
+    """BFS over a p_r x p_c grid of DCSC shares, step by step as Algorithm 3
+    (section 3.2) states it, on one host: per level the frontier f (sorted
+    global ids, each carrying its own id as the selected value) is split by
+    column block (the vector transpose and column gather); every share
+    multiplies its column block's piece (the local SpMSpV, with this
+    oracle's own SpMSpV); the pieces of a row block are folded with min (the
+    row exchange and merge at the owner); vertices without a parent yet take
+    the folded value as parent and form the next frontier (pi <- pi + t,
+    f <- t, with the mask of unvisited vertices). Returns (parent, level)."""
+    parent = np.full(n, -1, np.int64)
+    level = np.full(n, -1, np.int64)
+    parent[root] = root
+    level[root] = 0
+    f = np.array([root], np.int64)
+    k = 0
+    while f.size:
+        k += 1
+        t = np.full(n, np.iinfo(np.int64).max, np.int64)
+        for j in range(pc):
+            fj = f[(f >= j * C) & (f < (j + 1) * C)]
+            if not fj.size:
+                continue
+            local = (fj - j * C).astype(np.int32)
+            for i in range(pr):
+                oi, ov = spmspv_block(shares[i * pc + j], local, fj.astype(np.int32))
+                rows = oi.astype(np.int64) + i * R
+                np.minimum.at(t, rows, ov.astype(np.int64))
+        new = np.nonzero((t != np.iinfo(np.int64).max) & (parent == -1))[0]
+        parent[new] = t[new]
+        level[new] = k
+        f = new
+    return parent.astype(np.int32), level.astype(np.int32)

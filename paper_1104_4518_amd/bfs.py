@@ -132,6 +132,7 @@ def load(build_if_missing: bool = True):
         "bfs_spmspv": [_vp, ctypes.POINTER(SVec), ctypes.POINTER(SVec), _vp],
         "bfs_run_batch": [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_i32), ctypes.POINTER(_vp),
                           ctypes.POINTER(_vp), _vp],
+        "bfs_run_2d": [ctypes.POINTER(_vp), _i32, _i32, _i64, _i32, _vp, _vp, _vp],
         "bfs_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)],
         "bfs_server_submit": [_vp, _vp, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)],
         "bfs_server_poll": [_vp, ctypes.c_uint64, ctypes.POINTER(Result)],
@@ -327,6 +328,15 @@ def run_batch(graphs: Sequence[Graph], roots, parents, levels=None, stream=None)
     lv = (_vp * cnt)(*[(_ptr(x) if x is not None else None) for x in
                        (levels if levels is not None else [None] * cnt)])
     _check(lib.bfs_run_batch(cnt, hs, rs, ps, lv, _stream(stream)), "bfs_run_batch")
+
+
+def run_2d(shares: Sequence[Graph], pr: int, pc: int, n: int, root: int, parent, level=None,
+           stream=None) -> None:
+    """BFS over a p_r x p_c grid of DCSC share handles (row-major), device outputs."""
+    cnt = len(shares)
+    hs = (_vp * cnt)(*[g.handle for g in shares])
+    _check(load().bfs_run_2d(hs, int(pr), int(pc), int(n), int(root), _ptr(parent), _ptr(level),
+                             _stream(stream)), "bfs_run_2d")
 
 
 class Server:

@@ -207,3 +207,25 @@ def test_planted_max_semiring_is_caught():
     vals = np.where(a[:, f], f[None, :], -1).max(axis=1)
     got = [int(v) for v in vals if v >= 0]
     assert got != case["out_val"]
+
+
+@pytest.mark.parametrize("pr,pc", [(1, 1), (2, 2), (2, 3), (4, 4), (3, 1), (1, 5)])
+def test_bfs_2d_equals_queue_bfs(pr, pc):
+    """Algorithm 3 over a p_r x p_c grid of shares (the oracle's SpMSpV per
+    share, min-fold per row block, mask) gives the queue BFS's parents and
+    levels: undirected R-MAT, a grid, and a directed graph."""
+    rng = np.random.default_rng(pr * 10 + pc)
+    graphs = [graphgen.rmat_csr(10, 8, 3 + pr), graphgen.grid_csr(17, 9)]
+    n = 700
+    src, dst = rng.integers(0, n, 4000), rng.integers(0, n, 4000)
+    order = np.lexsort((dst, src))
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(np.bincount(src[order], minlength=n))
+    graphs.append(graphgen.CSR(n, off, dst[order].astype(np.int32)))
+    for g in graphs:
+        R, C, shares = graphgen.csr_to_2d(g, pr, pc)
+        assert sum(s.nnz for s in shares) == g.nnz
+        for r in graphgen.roots(g, 3, 7):
+            p2, l2 = oracle.bfs_2d(g.n, R, C, pr, pc, shares, int(r))
+            p1, l1 = oracle.bfs_graph(g, int(r))
+            assert np.array_equal(p2, p1) and np.array_equal(l2, l1)

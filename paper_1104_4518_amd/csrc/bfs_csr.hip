@@ -514,6 +514,33 @@ constexpr int kResolveBlock = 1024;
 constexpr int kResolveRV = 4;
 constexpr int kFirst = 8;
 
+// Bitmap of the hot prefix's vertices at level k-1 (mark byte = its tag),
+// built once per mark level for k_resolve's workgroups to copy into LDS.
+__global__ void k_prev_bits(const uint8_t* __restrict__ mark, const LevelState* __restrict__ st,
+                            int cbits, MarkPolicy mp, int hw, uint32_t* __restrict__ prev_bits) {
+  const int k = st->k_fold;
+  const unsigned long long cmask = (1ull << cbits) - 1;
+  const unsigned long long cin = st->ctr[(k - 1) % 3];
+  if ((cin & cmask) == 0 || !mark_level(cin, cbits, mp)) return;
+  if ((int64_t)(st->ctr[k % 3] & cmask) < ((int64_t)hw << 5)) return;   // k_resolve won't stage
+  const uint4* __restrict__ mark4 = reinterpret_cast<const uint4*>(mark);
+  const uint32_t tp4 = 0x01010101u * level_tag(k - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < hw; i += stride) {
+    const uint4 a = mark4[2 * i], b = mark4[2 * i + 1];
+    const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t bits = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const uint32_t e = x[t] ^ tp4;   // zero bytes = tag of level k-1
+#pragma unroll
+      for (int byte = 0; byte < 4; ++byte)
+        if (((e >> (8 * byte)) & 0xFFu) == 0u) bits |= 1u << (4 * t + byte);
+    }
+    prev_bits[i] = bits;
+  }
+}
+
 __device__ __forceinline__ bool prev_level(int32_t u, int64_t hotv, const uint32_t* s_prev,
                                            const uint8_t* __restrict__ mark, uint8_t tprev) {
   return u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u : mark[u] == tprev;
@@ -522,7 +549,8 @@ __device__ __forceinline__ bool prev_level(int32_t u, int64_t hotv, const uint32
 __global__ __launch_bounds__(kResolveBlock) void k_resolve(
     const int32_t* __restrict__ col, int32_t* __restrict__ parent, int32_t* __restrict__ level,
     const uint8_t* __restrict__ mark, Queues q, const LevelState* __restrict__ st, int cbits,
-    MarkPolicy mp, const int32_t* __restrict__ inv, int hw) {
+    MarkPolicy mp, const int32_t* __restrict__ inv, int hw,
+    const uint32_t* __restrict__ prev_bits) {
   __shared__ uint32_t s_prev[kHotWordsMax];
   const int k = st->k_fold;
   const unsigned long long cmask = (1ull << cbits) - 1;
@@ -537,24 +565,11 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
   const uint8_t tprev = level_tag(k - 1);
   const int tid = threadIdx.x;
   const int lane = lane_id();
-  // stage the hot prefix only when the frontier is large enough to repay it
+  // stage the hot prefix (built once by k_prev_bits) only when the
+  // frontier is large enough to repay it
   const int64_t hotv = F >= ((int64_t)hw << 5) ? ((int64_t)hw << 5) : 0;
   if (hotv) {
-    const uint4* __restrict__ mark4 = reinterpret_cast<const uint4*>(mark);
-    const uint32_t tp4 = 0x01010101u * tprev;
-    for (int i = tid; i < hw; i += kResolveBlock) {
-      const uint4 a = mark4[2 * i], b = mark4[2 * i + 1];
-      const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-      uint32_t bits = 0;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const uint32_t e = x[t] ^ tp4;   // zero bytes = tag tprev
-#pragma unroll
-        for (int byte = 0; byte < 4; ++byte)
-          if (((e >> (8 * byte)) & 0xFFu) == 0u) bits |= 1u << (4 * t + byte);
-      }
-      s_prev[i] = bits;
-    }
+    for (int i = tid; i < hw; i += kResolveBlock) s_prev[i] = prev_bits[i];
     __syncthreads();
   }
   const int64_t chunk = (int64_t)kResolveBlock * kResolveRV;
@@ -607,20 +622,49 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
       for (int i = kFirst - 1; i >= 0; --i)
         if (i < hh[t] && cm[t][i] == tprev) p[t] = u[t][i];
     }
+    // continuation up to kSerialScan adjacencies, four per step, the RV
+    // searches of the thread advancing together (their loads overlap)
     bool pending[kResolveRV];
+    {
+      int64_t e[kResolveRV], lim[kResolveRV];
 #pragma unroll
-    for (int t = 0; t < kResolveRV; ++t) {
-      // serial continuation up to kSerialScan adjacencies
-      const int64_t lim = min(end[t], o[t] + (int64_t)kSerialScan);
-      for (int64_t e = o[t] + kFirst; e < lim && p[t] < 0; e += 4) {
-        int32_t w4[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) w4[i] = e + i < lim ? col[e + i] : -1;
-#pragma unroll
-        for (int i = 3; i >= 0; --i)
-          if (w4[i] >= 0 && prev_level(w4[i], hotv, s_prev, mark, tprev)) p[t] = w4[i];
+      for (int t = 0; t < kResolveRV; ++t) {
+        e[t] = o[t] + kFirst;
+        lim[t] = min(end[t], o[t] + (int64_t)kSerialScan);
       }
-      pending[t] = v[t] >= 0 && p[t] < 0 && end[t] - o[t] > kSerialScan;
+      for (;;) {
+        bool any = false;
+        int32_t w4[kResolveRV][4];
+#pragma unroll
+        for (int t = 0; t < kResolveRV; ++t) {
+          const bool act = p[t] < 0 && e[t] < lim[t];
+          any |= act;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) w4[t][i] = (act && e[t] + i < lim[t]) ? col[e[t] + i] : -1;
+        }
+        if (!any) break;
+        uint8_t m4[kResolveRV][4];
+#pragma unroll
+        for (int t = 0; t < kResolveRV; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            m4[t][i] = (w4[t][i] >= hotv) ? mark[w4[t][i]] : (uint8_t)0;
+#pragma unroll
+        for (int t = 0; t < kResolveRV; ++t) {
+#pragma unroll
+          for (int i = 3; i >= 0; --i) {
+            const int32_t u = w4[t][i];
+            if (u < 0) continue;
+            const bool hit = u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u
+                                      : m4[t][i] == tprev;
+            if (hit) p[t] = u;
+          }
+          e[t] += 4;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kResolveRV; ++t)
+        pending[t] = v[t] >= 0 && p[t] < 0 && end[t] - o[t] > kSerialScan;
     }
     // the wave scans the rest of each long adjacency list together
 #pragma unroll
@@ -784,6 +828,8 @@ int csr_alloc_workspace(bfs_graph* g) {
     c.hot_words = (int)std::min<int64_t>(std::max<int64_t>(c.nwords, 1), kHotWordsMax);
     c.hot_slices = mark_expand_grid(g->device);
     BFS_HIP(hipMalloc(&c.hot_new, (size_t)c.hot_slices * c.hot_words * 4));
+    BFS_HIP(hipMalloc(&c.prev_bits, (size_t)c.hot_words * 4));
+    g->device_bytes += (int64_t)c.hot_words * 4;
     g->device_bytes += (int64_t)c.hot_slices * c.hot_words * 4;
   }
   g->device_bytes += std::max<int64_t>(c.nwords, 1) * 4 + c.n * 44 + c.njstart * 8 +
@@ -805,6 +851,7 @@ void csr_free(bfs_graph* g) {
   (void)hipFree(c.zq);
   (void)hipFree(c.mark);
   (void)hipFree(c.hot_new);
+  (void)hipFree(c.prev_bits);
   (void)hipFree(c.state);
   if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
   if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
@@ -988,9 +1035,12 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
                                                         c.njstart, c.zq, c.state, c.cbits, c.n,
                                                         c.nwords, mp, c.hot_words, c.hot_new,
                                                         gm);
-    if (mp.symmetric)
+    if (mp.symmetric) {
+      k_prev_bits<<<(c.hot_words + 255) / 256, 256, 0, st>>>(c.mark, c.state, c.cbits, mp,
+                                                             c.hot_words, c.prev_bits);
       k_resolve<<<gr, kResolveBlock, 0, st>>>(kcol, d_parent, d_level, c.mark, q, c.state,
-                                              c.cbits, mp, kinv, c.hot_words);
+                                              c.cbits, mp, kinv, c.hot_words, c.prev_bits);
+    }
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
     return BFS_OK;
   };

@@ -86,6 +86,7 @@ struct CsrDev {
   int hot_words = 0;
   int hot_slices = 0;
   uint32_t* hot_new = nullptr;
+  uint32_t* prev_bits = nullptr;  // hot prefix's vertices one level up (resolve)
 
   int32_t* jstart = nullptr;     // first queue entry of each expand tile
   int64_t njstart = 0;

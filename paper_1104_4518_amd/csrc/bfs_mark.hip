@@ -71,41 +71,53 @@ __device__ __forceinline__ void tile_targets(const int32_t* __restrict__ col,
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // Row and position of each edge, then its target. A staged tile takes
-  // each row's adjacency start from the owning lane (an LDS-path shuffle, so
-  // the adjacency loads never wait on one another); a tile of more than 64
-  // rows gathers it from the queue. Edges past the tile's end load col[0]
-  // and are dropped.
+  // Row of each edge (the number of row starts at or before it), then its
+  // target. In a staged tile lane r holds row r's adjacency start minus its
+  // tile-relative edge prefix, so an edge's adjacency index is that value
+  // (shuffled from its row's lane, an LDS-path operation: the adjacency loads
+  // never wait on one another) plus its position in the tile. A tile of more
+  // than 64 rows gathers the row start from the queue and derives the
+  // position in the row from the last start at or before the edge. The start
+  // masks are the same for the whole wave (readfirstlane keeps their
+  // bookkeeping scalar). Edges past the tile's end load col[0] and are
+  // dropped.
   const uint32_t lo_below = lane < 32 ? (2u << lane) - 1u : 0xFFFFFFFFu;
   const uint32_t hi_below = lane < 32 ? 0u : (2u << (lane - 32)) - 1u;
-  int base = 0;            // row starts before this step's window
-  int carry = row0_pos;    // position of the window's first edge in row `base`
-  const int64_t* __restrict__ qo_t = qo_in + t.j0;
-#define BFS_TILE_STEP(ROW_START)                                                         \
-  for (int i = 0; i < STEPS; ++i) {                                                      \
-    const uint32_t mlo = starts[2 * i], mhi = starts[2 * i + 1];                         \
-    const uint32_t blo = mlo & lo_below, bhi = mhi & hi_below;                           \
-    const int c = __popc(blo) + __popc(bhi);                                             \
-    const int last = bhi ? 63 - __clz(bhi) : 31 - __clz(blo); /* last start <= lane */   \
-    const int row = base + c; /* <= number of starts <= R - 1 */                         \
-    const int pos = c ? lane - last : carry + lane;                                      \
-    base += __popc(mlo) + __popc(mhi);                                                   \
-    carry = mhi ? 64 - (63 - __clz(mhi)) : (mlo ? 64 - (31 - __clz(mlo)) : carry + 64); \
-    const bool ok = i * 64 + lane < n_e;                                                 \
-    const int64_t ro = (ROW_START);                                                      \
-    const int32_t x = col[ok ? ro + pos : 0];                                            \
-    vv[i] = ok ? x : -1;                                                                 \
-  }
-  // (carry: the next window's first edge is just past the last start seen,
-  // or 64 further along the same row)
+  int base = 0;   // row starts before this step's window
   if (staged) {
+    const int64_t cb = t.qo - t.qe + e0;
 #pragma unroll
-    BFS_TILE_STEP(shfl_ll(t.qo, row & 63))
+    for (int i = 0; i < STEPS; ++i) {
+      const uint32_t mlo = __builtin_amdgcn_readfirstlane(starts[2 * i]);
+      const uint32_t mhi = __builtin_amdgcn_readfirstlane(starts[2 * i + 1]);
+      const int row = base + __popc(mlo & lo_below) + __popc(mhi & hi_below);   // <= R - 1
+      base += __popc(mlo) + __popc(mhi);
+      const int e = i * 64 + lane;
+      const bool ok = e < n_e;
+      const int32_t x = col[ok ? shfl_ll(cb, row & 63) + e : 0];
+      vv[i] = ok ? x : -1;
+    }
   } else {
+    int carry = row0_pos;    // position of the window's first edge in row `base`
+    const int64_t* __restrict__ qo_t = qo_in + t.j0;
 #pragma unroll
-    BFS_TILE_STEP(qo_t[row])
+    for (int i = 0; i < STEPS; ++i) {
+      const uint32_t mlo = __builtin_amdgcn_readfirstlane(starts[2 * i]);
+      const uint32_t mhi = __builtin_amdgcn_readfirstlane(starts[2 * i + 1]);
+      const uint32_t blo = mlo & lo_below, bhi = mhi & hi_below;
+      const int c = __popc(blo) + __popc(bhi);
+      const int last = bhi ? 63 - __clz(bhi) : 31 - __clz(blo);   // last start <= lane
+      const int row = base + c;                                    // <= R - 1
+      const int pos = c ? lane - last : carry + lane;
+      base += __popc(mlo) + __popc(mhi);
+      // the next window's first edge: just past the last start seen, or 64
+      // further along the same row
+      carry = mhi ? 64 - (63 - __clz(mhi)) : (mlo ? 64 - (31 - __clz(mlo)) : carry + 64);
+      const bool ok = i * 64 + lane < n_e;
+      const int32_t x = col[ok ? qo_t[row] + pos : 0];
+      vv[i] = ok ? x : -1;
+    }
   }
-#undef BFS_TILE_STEP
 }
 
 // expand(k), mark levels. One 1024-thread workgroup per CU keeps the first

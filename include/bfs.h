@@ -272,9 +272,10 @@ typedef struct bfs_server_config {
   int32_t step_budget_us;   /* a device step stops advancing a query at the first level
                                boundary after this many microseconds (0 = 400) */
   int64_t large_query_nnz;  /* queries on graphs with at least this many adjacencies and an
-                               average degree >= 8 run one at a time across the whole GPU on
-                               a second stream instead of in the multi-query steps
-                               (0 = 2^23, -1 = never) */
+                               average degree >= 8 (few levels) run one at a time across the
+                               whole GPU on a second stream instead of in the multi-query
+                               steps, where one workgroup per query would take far longer
+                               (0 = 2^16, -1 = never) */
 } bfs_server_config_t;
 
 typedef struct bfs_result {

@@ -291,7 +291,7 @@ int bfs_server_create(const bfs_server_config_t* cfg, bfs_server_t** out) {
     };
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->lane_stream, hipStreamNonBlocking);
-    s->large_nnz = cfg->large_query_nnz == 0 ? ((int64_t)1 << 23) : cfg->large_query_nnz;
+    s->large_nnz = cfg->large_query_nnz == 0 ? ((int64_t)1 << 16) : cfg->large_query_nnz;
     const size_t nq = (size_t)cfg->slots;
     if (e == hipSuccess) e = hipMalloc(&s->d_qs, nq * sizeof(MQuery));
     if (e == hipSuccess) e = hipMalloc(&s->d_active, nq * 4);

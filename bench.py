@@ -19,8 +19,8 @@ The JSON line also carries:
                 local products, 50 at each frontier density, p50 per density
   mix           1024 queries over R-MAT scales 14-22 and 512^2 / 2048^2
                 grids: one-at-a-time plain path, one batched launch, and the
-                continuous-batching server under Poisson arrivals at 0.5x and
-                4x the plain path's capacity (GTEPS, p50/p99 latency)
+                continuous-batching server under Poisson arrivals at 0.5x, 4x
+                and 16x the plain path's capacity (GTEPS, p50/p99 latency)
 """
 from __future__ import annotations
 
@@ -121,6 +121,12 @@ def bfs_leg(args, torch, graphgen, B):
     roots = graphgen.config_roots(args.workload, g)
     log(f"graph n={g.n} nnz={g.nnz} in {time.time() - t0:.1f}s; {len(roots)} roots")
     G = B.Graph.from_csr(g.n, g.off, g.col, trusted=True, symmetric=True)
+    t_tune = time.time()
+    G.tune()   # launch shapes and mark-level floor, measured on this graph (untimed)
+    opt = G.get_options()
+    tuned = {"grid_blocks": opt.grid_blocks, "batch_levels": opt.batch_levels,
+             "claim_min_frontier": opt.claim_min_frontier}
+    log(f"tuned in {time.time() - t_tune:.1f}s: {tuned}")
     G.set_options(profile=1)
     parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
     level = torch.empty(g.n, dtype=torch.int32, device="cuda")
@@ -180,6 +186,7 @@ def bfs_leg(args, torch, graphgen, B):
             "timed_roots_in_giant_component": len(giant),
             "timed_roots_outside": args.steps - len(giant),
             "graph_hash": hex(g.hash()),
+            "tuned_options": tuned,
         },
         "roofline": {
             "bound": "hbm",
@@ -319,7 +326,7 @@ def mix_leg(torch, graphgen, B, np, nq: int):
 
     served = {}
     cap_qps = nq / plain_s
-    for factor in (0.5, 4.0):
+    for factor in (0.5, 4.0, 16.0):
         qps = factor * cap_qps
         arrivals = graphgen.poisson_arrivals(nq, qps, 2000 + int(factor * 10))
         S = B.Server(slots=512)
@@ -338,6 +345,7 @@ def mix_leg(torch, graphgen, B, np, nq: int):
         served[f"{factor:g}x"] = {
             "qps": round(qps, 2),
             "gteps": round(m_served / span / 1e9, 4),
+            "vs_plain": round(m_served / span / 1e9 / max(plain["gteps"], 1e-9), 2),
             "p50_ms": round(pct(lat, 50), 3),
             "p99_ms": round(pct(lat, 99), 3),
             "span_s": round(span, 3),

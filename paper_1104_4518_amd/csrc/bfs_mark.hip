@@ -94,7 +94,10 @@ __device__ __forceinline__ void tile_targets(const int32_t* __restrict__ col,
       base += __popc(mlo) + __popc(mhi);
       const int e = i * 64 + lane;
       const bool ok = e < n_e;
-      const int32_t x = col[ok ? shfl_ll(cb, row & 63) + e : 0];
+      // the shuffle runs in every lane (an inactive source lane would give
+      // an undefined value); only the index is selected afterwards
+      const int64_t rb = shfl_ll(cb, row & 63);
+      const int32_t x = col[ok ? rb + e : 0];
       vv[i] = ok ? x : -1;
     }
   } else {

@@ -122,7 +122,7 @@ def bfs_leg(args, torch, graphgen, B):
     log(f"graph n={g.n} nnz={g.nnz} in {time.time() - t0:.1f}s; {len(roots)} roots")
     G = B.Graph.from_csr(g.n, g.off, g.col, trusted=True, symmetric=True)
     t_tune = time.time()
-    G.tune()   # launch shapes and mark-level floor, measured on this graph (untimed)
+    G.tune(args.tune_cache)   # launch shapes and mark-level floor, measured on this graph (untimed)
     opt = G.get_options()
     tuned = {"grid_blocks": opt.grid_blocks, "batch_levels": opt.batch_levels,
              "claim_min_frontier": opt.claim_min_frontier}
@@ -372,6 +372,9 @@ def main() -> int:
     ap.add_argument("--workload", default="rmat22", choices=["rmat12", "rmat22", "rmat26", "er26"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="text file the launch-shape tuning is read from / appended to, so "
+                         "profiled runs reuse an earlier run's choice without timing sweeps")
     ap.add_argument("--legs", default="bfs,spmspv,mix",
                     help="comma list of legs to run: bfs, spmspv, mix")
     ap.add_argument("--mix-queries", type=int, default=1024)

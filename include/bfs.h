@@ -102,10 +102,14 @@ typedef struct bfs_run_stats {
   int64_t frontier_total;    /* sum of frontier sizes over all levels */
   int32_t expand_launches;   /* levels enqueued, including empty speculative ones */
   int32_t mark_levels;       /* levels resolved by mark-and-resolve instead of atomicMin */
-  double expand_ms;          /* summed device time of the levels' expand launches, claim and
-                                mark kernels (options.profile = 1) */
+  double expand_ms;          /* summed device time of the levels' expand launches, claim,
+                                mark and pull kernels (options.profile = 1) */
   double mark_ms;            /* the mark-and-resolve expand kernel's share of expand_ms */
   double total_ms;           /* device time of the whole run (options.profile = 1) */
+  int32_t pull_levels;       /* mark levels whose product was computed by rows (pull) */
+  int32_t reserved;
+  double pull_ms;            /* the pull kernel's share of expand_ms */
+  int64_t pull_edges;        /* adjacencies examined by the pull levels */
 } bfs_run_stats_t;
 
 /* Run-time tuning knobs of a graph handle (0 = keep the current value). */
@@ -135,6 +139,11 @@ typedef struct bfs_options {
                               8192) take the single-workgroup sort path when their product
                               fits it, larger ones the sparse accumulator; -1 = never
                               (0 = keep; default 512; bfs_tune measures it) */
+  int32_t pull_alpha;   /* a mark level computes its product by rows (every unvisited vertex
+                           searches its ascending adjacency list for the first vertex of the
+                           frontier) instead of pushing the frontier's adjacencies when
+                           pull_alpha * (frontier adjacencies) >= adjacencies of the
+                           vertices not yet visited; -1 = never (0 = keep; default 14) */
 } bfs_options_t;
 
 /* ---------------------------------------------------------------- graphs */
@@ -197,12 +206,15 @@ int bfs_last_stats(bfs_graph_t* g, bfs_run_stats_t* st);
 /* One level of the last profiled run. */
 typedef struct bfs_level_info {
   int32_t level;        /* k: the level whose vertices this step discovered */
-  int32_t mark;         /* 1 = mark-and-resolve, 0 = atomicMin claims */
+  int32_t mark;         /* 1 = mark-and-resolve, 2 = pull (by rows), 0 = atomicMin claims */
   int64_t frontier;     /* vertices of frontier k-1 that were expanded */
   int64_t edges;        /* their adjacencies */
-  double expand_ms;     /* device time of the level's expand launches (claim and mark) */
+  double expand_ms;     /* device time of the level's expand launches (claim, mark, pull) */
   double mark_ms;       /* the mark expand kernel's share of expand_ms */
   double finish_ms;     /* device time of its finish and resolve launches */
+  double pull_ms;       /* the pull kernel's share of expand_ms */
+  int64_t pull_candidates; /* pull levels: unvisited vertices of positive degree (searchers) */
+  int64_t pull_edges;   /* pull levels: adjacencies they examined */
 } bfs_level_info_t;
 
 /*

@@ -54,14 +54,17 @@ class RunStats(ctypes.Structure):
                 ("edges_traversed", ctypes.c_int64), ("reached", ctypes.c_int64),
                 ("frontier_total", ctypes.c_int64), ("expand_launches", ctypes.c_int32),
                 ("mark_levels", ctypes.c_int32), ("expand_ms", ctypes.c_double),
-                ("mark_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("mark_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("pull_levels", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pull_ms", ctypes.c_double), ("pull_edges", ctypes.c_int64)]
 
 
 class LevelInfo(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("mark", ctypes.c_int32),
                 ("frontier", ctypes.c_int64), ("edges", ctypes.c_int64),
                 ("expand_ms", ctypes.c_double), ("mark_ms", ctypes.c_double),
-                ("finish_ms", ctypes.c_double)]
+                ("finish_ms", ctypes.c_double), ("pull_ms", ctypes.c_double),
+                ("pull_candidates", ctypes.c_int64), ("pull_edges", ctypes.c_int64)]
 
 
 class Options(ctypes.Structure):
@@ -69,7 +72,8 @@ class Options(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32), ("lds_bitmap", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("claim", ctypes.c_int32),
                 ("claim_threshold", ctypes.c_int32), ("claim_min_frontier", ctypes.c_int32),
-                ("cold_probe", ctypes.c_int32), ("spmspv_sort_max", ctypes.c_int32)]
+                ("cold_probe", ctypes.c_int32), ("spmspv_sort_max", ctypes.c_int32),
+                ("pull_alpha", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -267,9 +271,9 @@ class Graph:
 
     def set_options(self, mode=0, batch_levels=0, grid_blocks=0, lds_bitmap=0, profile=0,
                     claim=0, claim_threshold=0, claim_min_frontier=0, cold_probe=0,
-                    spmspv_sort_max=0):
+                    spmspv_sort_max=0, pull_alpha=0):
         o = Options(mode, batch_levels, grid_blocks, lds_bitmap, profile, claim, claim_threshold,
-                    claim_min_frontier, cold_probe, spmspv_sort_max)
+                    claim_min_frontier, cold_probe, spmspv_sort_max, pull_alpha)
         _check(load().bfs_graph_set_options(self.handle, ctypes.byref(o)),
                "bfs_graph_set_options")
 

@@ -54,6 +54,7 @@ void default_options(bfs_options_t* o) {
   o->claim_min_frontier = 0;
   o->cold_probe = 3;
   o->spmspv_sort_max = 512;
+  o->pull_alpha = 14;
 }
 
 }  // namespace
@@ -235,9 +236,12 @@ int bfs_graph_set_options(bfs_graph_t* g, const bfs_options_t* opt) {
     return fail(BFS_ERR_ARG, "option out of range");
   if (opt->cold_probe < 0 || opt->cold_probe > 3)
     return fail(BFS_ERR_ARG, "cold_probe must be 1, 2 or 3");
-  if (opt->cold_probe) g->opt.cold_probe = opt->cold_probe;
   if (opt->spmspv_sort_max < -1) return fail(BFS_ERR_ARG, "spmspv_sort_max must be >= -1");
+  if (opt->pull_alpha < -1) return fail(BFS_ERR_ARG, "pull_alpha must be >= -1");
+  // every field checked: apply
+  if (opt->cold_probe) g->opt.cold_probe = opt->cold_probe;
   if (opt->spmspv_sort_max) g->opt.spmspv_sort_max = opt->spmspv_sort_max;
+  if (opt->pull_alpha) g->opt.pull_alpha = opt->pull_alpha;
   if (opt->claim) g->opt.claim = opt->claim;
   if (opt->claim_threshold) g->opt.claim_threshold = opt->claim_threshold;
   if (opt->claim_min_frontier) g->opt.claim_min_frontier = opt->claim_min_frontier;

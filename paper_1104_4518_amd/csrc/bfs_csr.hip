@@ -95,6 +95,9 @@ __global__ void k_seed(const int64_t* __restrict__ off, int32_t root, int32_t* p
   st->zcnt[0] = st->zcnt[1] = st->zcnt[2] = 0u;
   st->error = 0;
   st->mark_levels = 0;
+  st->pull = 0;
+  st->pull_levels = 0;
+  st->pull_edges = 0ull;
 }
 
 // Block-wide exclusive scan of (count, degree sum) pairs; returns the
@@ -177,15 +180,30 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     st->ctr[(k + 1) % 3] = 0ull;   // output counters of level k + 1
     st->zcnt[(k + 1) % 3] = 0u;
     st->k_fold = k;
+    int pull = 0;
     if (F > 0) {
       st->levels = k;
       st->edges += (unsigned long long)T;
       st->frontier_total += (unsigned long long)F;
-      if (mark_level(cin, cbits, mp)) st->mark_levels += 1;
+      if (mark_level(cin, cbits, mp)) {
+        st->mark_levels += 1;
+        // direction of the product: by rows once the frontier's adjacencies
+        // outweigh (by pull_alpha) those of the vertices still unvisited,
+        // which the pull would examine at most
+        const unsigned long long seen = st->edges;
+        const unsigned long long rest =
+            (unsigned long long)mp.nnz > seen ? (unsigned long long)mp.nnz - seen : 0ull;
+        pull = mp.pull_alpha > 0 &&
+               (unsigned long long)T * (unsigned long long)mp.pull_alpha >= rest;
+        st->pull_levels += pull;
+      }
     }
+    st->pull = pull;
     if (k < kLevelHist) {
       st->hist[k] = cin;
-      st->hist_mark[k] = mark_level(cin, cbits, mp) ? 1 : 0;
+      st->hist_mark[k] = pull ? 2 : (mark_level(cin, cbits, mp) ? 1 : 0);
+      st->hist_pc[k] = 0ull;
+      st->hist_pe[k] = 0ull;
     }
   }
   if (F == 0 || mark_level(cin, cbits, mp)) return;
@@ -364,7 +382,8 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   // mark level: collect the touched vertices one 32-vertex word per thread
   // (marks beyond the hot prefix, the OR of the expand workgroups' slices
   // within it), append them to the next frontier in vertex order, set their
-  // visited bits and give them this level's tag. Parents come from k_resolve.
+  // visited bits and give them this level's tag. Parents come from k_resolve
+  // after a push, and were set by k_pull on a pull level.
   int32_t* __restrict__ jstart = jstart_base + (int64_t)(k & 1) * njs;
   int32_t* __restrict__ qv_out = q.qv[k & 1];
   int64_t* __restrict__ qo_out = q.qo[k & 1];
@@ -372,6 +391,9 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   unsigned long long* ctr_out = &st->ctr[k % 3];
   uint4* __restrict__ mark4 = reinterpret_cast<uint4*>(mark);
   const uint32_t tcur = level_tag(k);
+  // a pull level marks every vertex it reaches with a byte; the expand
+  // workgroups' hot slices belong to the last push level then
+  const int ns = st->pull ? 0 : nslices;
   unsigned int my_reached = 0;
   for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nwords; base += stride) {
     const int64_t w = base + tid;
@@ -386,13 +408,13 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
 #pragma unroll
         for (int byte = 0; byte < 4; ++byte)
           if (((x[i] >> (8 * byte)) & 0xFFu) == 1u) m |= 1u << (4 * i + byte);
-      if (w < hw) {
+      if (w < hw && ns) {
         uint32_t h[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
         int s = 0;
-        for (; s + 8 <= nslices; s += 8)
+        for (; s + 8 <= ns; s += 8)
 #pragma unroll
           for (int i = 0; i < 8; ++i) h[i] |= hot_new[(int64_t)(s + i) * hw + w];
-        for (; s < nslices; ++s) h[0] |= hot_new[(int64_t)s * hw + w];
+        for (; s < ns; ++s) h[0] |= hot_new[(int64_t)s * hw + w];
 #pragma unroll
         for (int i = 0; i < 8; ++i) m |= h[i];
       }
@@ -515,14 +537,15 @@ constexpr int kResolveRV = 4;
 constexpr int kFirst = 8;
 
 // Bitmap of the hot prefix's vertices at level k-1 (mark byte = its tag),
-// built once per mark level for k_resolve's workgroups to copy into LDS.
+// built once per mark level, ahead of its expand, for the workgroups of
+// k_resolve and k_pull to copy into LDS. No launch of level k changes a tag
+// of level k-1 (they only turn 0 into 1 and 1 into the tag of level k).
 __global__ void k_prev_bits(const uint8_t* __restrict__ mark, const LevelState* __restrict__ st,
                             int cbits, MarkPolicy mp, int hw, uint32_t* __restrict__ prev_bits) {
   const int k = st->k_fold;
   const unsigned long long cmask = (1ull << cbits) - 1;
   const unsigned long long cin = st->ctr[(k - 1) % 3];
   if ((cin & cmask) == 0 || !mark_level(cin, cbits, mp)) return;
-  if ((int64_t)(st->ctr[k % 3] & cmask) < ((int64_t)hw << 5)) return;   // k_resolve won't stage
   const uint4* __restrict__ mark4 = reinterpret_cast<const uint4*>(mark);
   const uint32_t tp4 = 0x01010101u * level_tag(k - 1);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -546,6 +569,138 @@ __device__ __forceinline__ bool prev_level(int32_t u, int64_t hotv, const uint32
   return u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u : mark[u] == tprev;
 }
 
+// First neighbour one level up (mark tag tprev, or a bit of the LDS bitmap
+// s_prev below hotv) in each of the thread's RV adjacency ranges
+// [o[t], end[t]): p[t] = that neighbour and at[t] = its position, or p[t] =
+// -1 and at[t] = end[t]. Entries with v[t] < 0 have empty ranges. The RV
+// searches of a thread test their first kFirst adjacencies together, then
+// advance four at a time up to kSerialScan; the wave finishes the longer
+// searches together, 64 adjacencies per step, so every lane of the wave
+// must make the call.
+template <int RV>
+__device__ __forceinline__ void first_up(const int32_t* __restrict__ col,
+                                         const uint8_t* __restrict__ mark,
+                                         const uint32_t* s_prev, int64_t hotv, uint8_t tprev,
+                                         int lane, const int32_t (&v)[RV], const int64_t (&o)[RV],
+                                         const int64_t (&end)[RV], int32_t (&p)[RV],
+                                         int64_t (&at)[RV]) {
+  // first kFirst adjacencies of all RV vertices together; the LDS tests of
+  // hot neighbours come first, so mark bytes are read only for the cold
+  // neighbours ahead of the first hot hit
+  int32_t u[RV][kFirst];
+#pragma unroll
+  for (int t = 0; t < RV; ++t)
+#pragma unroll
+    for (int i = 0; i < kFirst; ++i) u[t][i] = o[t] + i < end[t] ? col[o[t] + i] : -1;
+  int hh[RV];
+#pragma unroll
+  for (int t = 0; t < RV; ++t) {
+    hh[t] = kFirst;
+#pragma unroll
+    for (int i = kFirst - 1; i >= 0; --i)
+      if (u[t][i] >= 0 && u[t][i] < hotv && ((s_prev[u[t][i] >> 5] >> (u[t][i] & 31)) & 1u))
+        hh[t] = i;
+  }
+  uint8_t cm[RV][kFirst];
+#pragma unroll
+  for (int t = 0; t < RV; ++t)
+#pragma unroll
+    for (int i = 0; i < kFirst; ++i)
+      cm[t][i] = (i < hh[t] && u[t][i] >= hotv) ? mark[u[t][i]] : (uint8_t)0;
+#pragma unroll
+  for (int t = 0; t < RV; ++t) {
+    p[t] = hh[t] < kFirst ? u[t][hh[t] < kFirst ? hh[t] : 0] : -1;
+    at[t] = hh[t] < kFirst ? o[t] + hh[t] : end[t];
+#pragma unroll
+    for (int i = kFirst - 1; i >= 0; --i)
+      if (i < hh[t] && cm[t][i] == tprev) {
+        p[t] = u[t][i];
+        at[t] = o[t] + i;
+      }
+  }
+  // continuation up to kSerialScan adjacencies, four per step, the RV
+  // searches of the thread advancing together (their loads overlap)
+  bool pending[RV];
+  {
+    int64_t e[RV], lim[RV];
+#pragma unroll
+    for (int t = 0; t < RV; ++t) {
+      e[t] = o[t] + kFirst;
+      lim[t] = min(end[t], o[t] + (int64_t)kSerialScan);
+    }
+    for (;;) {
+      bool any = false;
+      int32_t w4[RV][4];
+#pragma unroll
+      for (int t = 0; t < RV; ++t) {
+        const bool act = p[t] < 0 && e[t] < lim[t];
+        any |= act;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w4[t][i] = (act && e[t] + i < lim[t]) ? col[e[t] + i] : -1;
+      }
+      if (!any) break;
+      uint8_t m4[RV][4];
+#pragma unroll
+      for (int t = 0; t < RV; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          m4[t][i] = (w4[t][i] >= hotv) ? mark[w4[t][i]] : (uint8_t)0;
+#pragma unroll
+      for (int t = 0; t < RV; ++t) {
+#pragma unroll
+        for (int i = 3; i >= 0; --i) {
+          const int32_t u = w4[t][i];
+          if (u < 0) continue;
+          const bool hit = u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u
+                                    : m4[t][i] == tprev;
+          if (hit) {
+            p[t] = u;
+            at[t] = e[t] + i;
+          }
+        }
+        e[t] += 4;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < RV; ++t)
+      pending[t] = v[t] >= 0 && p[t] < 0 && end[t] - o[t] > kSerialScan;
+  }
+  // the wave scans the rest of each long adjacency list together
+#pragma unroll
+  for (int t = 0; t < RV; ++t) {
+    for (;;) {
+      const unsigned long long pend = wave_ballot(pending[t]);
+      if (!pend) break;
+      const int leader = __ffsll((long long)pend) - 1;
+      const int64_t lo = shfl_ll(o[t] + kSerialScan, leader);
+      const int64_t hi = shfl_ll(end[t], leader);
+      int32_t found = -1;
+      int64_t fat = hi;
+      for (int64_t e0 = lo; e0 < hi; e0 += 64) {
+        const int64_t e = e0 + lane;
+        int32_t uu = 0;
+        bool hit = false;
+        if (e < hi) {
+          uu = col[e];
+          hit = prev_level(uu, hotv, s_prev, mark, tprev);
+        }
+        const unsigned long long hb = wave_ballot(hit);
+        if (hb) {
+          const int src = __ffsll((long long)hb) - 1;
+          found = __shfl(uu, src, 64);
+          fat = e0 + src;
+          break;
+        }
+      }
+      if (lane == leader) {
+        p[t] = found;
+        at[t] = fat;
+        pending[t] = false;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kResolveBlock) void k_resolve(
     const int32_t* __restrict__ col, int32_t* __restrict__ parent, int32_t* __restrict__ level,
     const uint8_t* __restrict__ mark, Queues q, const LevelState* __restrict__ st, int cbits,
@@ -555,7 +710,7 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
   const int k = st->k_fold;
   const unsigned long long cmask = (1ull << cbits) - 1;
   const unsigned long long cin = st->ctr[(k - 1) % 3];
-  if ((cin & cmask) == 0 || !mark_level(cin, cbits, mp)) return;
+  if ((cin & cmask) == 0 || !mark_level(cin, cbits, mp) || st->pull) return;
   const unsigned long long c = st->ctr[k % 3];
   const int64_t F = (int64_t)(c & cmask);
   const int64_t T = (int64_t)(c >> cbits);
@@ -576,7 +731,7 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
   const int64_t stride = (int64_t)gridDim.x * chunk;
   for (int64_t base = (int64_t)blockIdx.x * chunk; base < F; base += stride) {
     int32_t v[kResolveRV], p[kResolveRV];
-    int64_t o[kResolveRV], end[kResolveRV];
+    int64_t o[kResolveRV], end[kResolveRV], at[kResolveRV];
     // queue entries of the RV vertices, loaded together (indices clamped so
     // the loads need no branch; entries past F are dropped)
 #pragma unroll
@@ -588,120 +743,138 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
       const int64_t oj = qo[jc], e0 = qe[jc], e1 = qe[jn];
       const bool ok = j < F;
       v[t] = ok ? vj : -1;
-      p[t] = -1;
       o[t] = ok ? oj : 0;
       end[t] = ok ? oj + ((jc + 1 < F ? e1 : T) - e0) : 0;
     }
-    // first kFirst adjacencies of all RV vertices together; the LDS tests of
-    // hot neighbours come first, so mark bytes are read only for the cold
-    // neighbours ahead of the first hot hit
-    int32_t u[kResolveRV][kFirst];
-#pragma unroll
-    for (int t = 0; t < kResolveRV; ++t)
-#pragma unroll
-      for (int i = 0; i < kFirst; ++i) u[t][i] = o[t] + i < end[t] ? col[o[t] + i] : -1;
-    int hh[kResolveRV];
-#pragma unroll
-    for (int t = 0; t < kResolveRV; ++t) {
-      hh[t] = kFirst;
-#pragma unroll
-      for (int i = kFirst - 1; i >= 0; --i)
-        if (u[t][i] >= 0 && u[t][i] < hotv && ((s_prev[u[t][i] >> 5] >> (u[t][i] & 31)) & 1u))
-          hh[t] = i;
-    }
-    uint8_t cm[kResolveRV][kFirst];
-#pragma unroll
-    for (int t = 0; t < kResolveRV; ++t)
-#pragma unroll
-      for (int i = 0; i < kFirst; ++i)
-        cm[t][i] = (i < hh[t] && u[t][i] >= hotv) ? mark[u[t][i]] : (uint8_t)0;
-#pragma unroll
-    for (int t = 0; t < kResolveRV; ++t) {
-      p[t] = hh[t] < kFirst ? u[t][hh[t] < kFirst ? hh[t] : 0] : -1;
-#pragma unroll
-      for (int i = kFirst - 1; i >= 0; --i)
-        if (i < hh[t] && cm[t][i] == tprev) p[t] = u[t][i];
-    }
-    // continuation up to kSerialScan adjacencies, four per step, the RV
-    // searches of the thread advancing together (their loads overlap)
-    bool pending[kResolveRV];
-    {
-      int64_t e[kResolveRV], lim[kResolveRV];
-#pragma unroll
-      for (int t = 0; t < kResolveRV; ++t) {
-        e[t] = o[t] + kFirst;
-        lim[t] = min(end[t], o[t] + (int64_t)kSerialScan);
-      }
-      for (;;) {
-        bool any = false;
-        int32_t w4[kResolveRV][4];
-#pragma unroll
-        for (int t = 0; t < kResolveRV; ++t) {
-          const bool act = p[t] < 0 && e[t] < lim[t];
-          any |= act;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) w4[t][i] = (act && e[t] + i < lim[t]) ? col[e[t] + i] : -1;
-        }
-        if (!any) break;
-        uint8_t m4[kResolveRV][4];
-#pragma unroll
-        for (int t = 0; t < kResolveRV; ++t)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            m4[t][i] = (w4[t][i] >= hotv) ? mark[w4[t][i]] : (uint8_t)0;
-#pragma unroll
-        for (int t = 0; t < kResolveRV; ++t) {
-#pragma unroll
-          for (int i = 3; i >= 0; --i) {
-            const int32_t u = w4[t][i];
-            if (u < 0) continue;
-            const bool hit = u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u
-                                      : m4[t][i] == tprev;
-            if (hit) p[t] = u;
-          }
-          e[t] += 4;
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < kResolveRV; ++t)
-        pending[t] = v[t] >= 0 && p[t] < 0 && end[t] - o[t] > kSerialScan;
-    }
-    // the wave scans the rest of each long adjacency list together
-#pragma unroll
-    for (int t = 0; t < kResolveRV; ++t) {
-      for (;;) {
-        const unsigned long long pend = wave_ballot(pending[t]);
-        if (!pend) break;
-        const int leader = __ffsll((long long)pend) - 1;
-        const int64_t lo = shfl_ll(o[t] + kSerialScan, leader);
-        const int64_t hi = shfl_ll(end[t], leader);
-        int32_t found = -1;
-        for (int64_t e0 = lo; e0 < hi; e0 += 64) {
-          const int64_t e = e0 + lane;
-          int32_t uu = 0;
-          bool hit = false;
-          if (e < hi) {
-            uu = col[e];
-            hit = prev_level(uu, hotv, s_prev, mark, tprev);
-          }
-          const unsigned long long hb = wave_ballot(hit);
-          if (hb) {
-            found = __shfl(uu, __ffsll((long long)hb) - 1, 64);
-            break;
-          }
-        }
-        if (lane == leader) {
-          p[t] = found;
-          pending[t] = false;
-        }
-      }
-    }
+    first_up<kResolveRV>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
 #pragma unroll
     for (int t = 0; t < kResolveRV; ++t) {
       if (v[t] < 0) continue;
       const int32_t vo = inv ? inv[v[t]] : v[t];
       parent[vo] = (inv && p[t] >= 0) ? inv[p[t]] : p[t];
       if (level) level[vo] = k;
+    }
+  }
+}
+
+// pull(k), the product of a level computed by rows: every unvisited vertex
+// of positive degree searches its ascending adjacency list for the first
+// vertex one level up (first_up), which is its parent; the masked product
+// of section 3.2 restricted to the rows the mask leaves, the same entries
+// as the push. A vertex that finds one gets its parent and level and is
+// marked touched (byte 1) for finish(k). Each wave takes 64 words of the
+// visited bitmap (2048 vertices), lists their unvisited vertices in LDS and
+// hands them to its lanes RV at a time, so the searches fill the wave.
+constexpr int kPullBlock = 1024;
+// hot prefix staged by the pull: 144 KiB of bits plus 8 KiB of wave lists
+constexpr int kPullHotWords = 36864;
+// searches per thread
+constexpr int kPullRV = 2;
+
+__global__ __launch_bounds__(kPullBlock) void k_pull(
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+    const uint32_t* __restrict__ vis, int32_t* __restrict__ parent, int32_t* __restrict__ level,
+    uint8_t* __restrict__ mark, LevelState* st, MarkPolicy mp, const int32_t* __restrict__ inv,
+    int hw, const uint32_t* __restrict__ prev_bits, int64_t n_active) {
+  constexpr int WAVES = kPullBlock / 64;
+  __shared__ uint32_t s_prev[kPullHotWords];
+  __shared__ int s_exw[WAVES][64];
+  __shared__ uint32_t s_m[WAVES][64];
+  __shared__ unsigned long long s_red[2][WAVES];
+  if (!st->pull) return;
+  const int k = st->k_fold;
+  const uint8_t tprev = level_tag(k - 1);
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wid = tid >> 6;
+  // the hot prefix goes to LDS when the unvisited vertices' adjacencies
+  // (what the searches read at most) number at least 4 per staged vertex
+  const int hwp = min(hw, kPullHotWords);
+  const unsigned long long seen = st->edges;
+  const unsigned long long rest =
+      (unsigned long long)mp.nnz > seen ? (unsigned long long)mp.nnz - seen : 0ull;
+  const int64_t hotv = rest >= ((unsigned long long)hwp << 7) ? ((int64_t)hwp << 5) : 0;
+  if (hotv)
+    for (int i = tid; i < hwp; i += kPullBlock) s_prev[i] = prev_bits[i];
+  __syncthreads();
+  const int64_t nw = (n_active + 31) >> 5;
+  const int64_t nchunks = (nw + 63) >> 6;
+  const int64_t nwaves = (int64_t)gridDim.x * WAVES;
+  unsigned long long my_cand = 0, my_edges = 0;
+  for (int64_t c = (int64_t)blockIdx.x * WAVES + wid; c < nchunks; c += nwaves) {
+    const int64_t w = (c << 6) + lane;
+    uint32_t m = 0u;
+    if (w < nw) {
+      m = ~vis[w];
+      const int64_t left = n_active - (w << 5);   // >= 1 for w < nw
+      if (left < 32) m &= (1u << left) - 1u;
+    }
+    const int cnt = __popc(m);
+    const int incl = (int)wave_incl_scan((long long)cnt);
+    const int total = __shfl(incl, 63, 64);
+    s_exw[wid][lane] = incl - cnt;
+    s_m[wid][lane] = m;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int r = 0; r < total; r += 64 * kPullRV) {
+      int32_t v[kPullRV], p[kPullRV];
+      int64_t o[kPullRV], end[kPullRV], at[kPullRV];
+#pragma unroll
+      for (int t = 0; t < kPullRV; ++t) {
+        const int i = r + t * 64 + lane;
+        v[t] = -1;
+        o[t] = 0;
+        end[t] = 0;
+        if (i < total) {
+          int lo = 0;   // last lane whose list starts at or before i
+#pragma unroll
+          for (int step = 32; step; step >>= 1)
+            if (lo + step <= 63 && s_exw[wid][lo + step] <= i) lo += step;
+          const int32_t vv =
+              (int32_t)((((c << 6) + lo) << 5) + select_bit(s_m[wid][lo], i - s_exw[wid][lo]));
+          v[t] = vv;
+          o[t] = off[vv];
+          end[t] = off[vv + 1];
+        }
+      }
+      first_up<kPullRV>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
+#pragma unroll
+      for (int t = 0; t < kPullRV; ++t) {
+        if (v[t] < 0) continue;
+        my_cand += end[t] > o[t];   // vertices of degree 0 have nothing to search
+        my_edges += (unsigned long long)((p[t] >= 0 ? at[t] + 1 : end[t]) - o[t]);
+        if (p[t] < 0) continue;
+        const int32_t vo = inv ? inv[v[t]] : v[t];
+        parent[vo] = inv ? inv[p[t]] : p[t];
+        if (level) level[vo] = k;
+        mark[v[t]] = 1;
+      }
+    }
+    // the wave's lists are rewritten by its next chunk
+    __builtin_amdgcn_wave_barrier();
+  }
+  // statistics: candidates and examined adjacencies of the level
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    my_cand += __shfl_xor(my_cand, d, 64);
+    my_edges += __shfl_xor(my_edges, d, 64);
+  }
+  if (lane == 0) {
+    s_red[0][wid] = my_cand;
+    s_red[1][wid] = my_edges;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long a = 0, b = 0;
+    for (int x = 0; x < WAVES; ++x) {
+      a += s_red[0][x];
+      b += s_red[1][x];
+    }
+    if (b) atomicAdd(&st->pull_edges, b);
+    if (k < kLevelHist && a) {
+      atomicAdd(&st->hist_pc[k], a);
+      atomicAdd(&st->hist_pe[k], b);
     }
   }
 }
@@ -942,6 +1115,9 @@ int csr_relabel(bfs_graph* g, const int64_t* host_off, hipStream_t s) {
   BFS_HIP(hipGetLastError());
   BFS_HIP(hipStreamSynchronize(s));
   c.relabeled = 1;
+  // degree-descending order: the vertices of positive degree come first
+  c.n_active = 0;
+  while (c.n_active < n && roff[(size_t)c.n_active + 1] > roff[(size_t)c.n_active]) ++c.n_active;
   g->device_bytes += (n + 1) * 8 + std::max<int64_t>(c.nnz, 1) * 4 + n * 8;
   return BFS_OK;
 }
@@ -962,6 +1138,8 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
                         ? (long long)g->opt.claim_min_frontier
                         : std::min<long long>(std::max<long long>(c.n / 1024, 1024), 4096);
   if (claim == 2) mp.min_edges = mp.min_vertices = 1;
+  mp.nnz = (long long)c.nnz;
+  mp.pull_alpha = g->opt.pull_alpha > 0 ? g->opt.pull_alpha : 0;
 
   int32_t* d_parent = parent;
   int32_t* d_level = level;
@@ -1005,10 +1183,13 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   // workgroups; the mark expand runs one 1024-thread workgroup per CU (its
   // LDS holds the hot prefix of the visited bitmap)
 
-  static int ge_cache = 0, gf_cache = 0, gr_cache = 0;
+  static int ge_cache = 0, gf_cache = 0, gr_cache = 0, gp_cache = 0;
   if (!ge_cache) ge_cache = grid_for(g->device, (const void*)k_expand<kExpandBlock>, kExpandBlock, 8);
   if (!gf_cache) gf_cache = grid_for(g->device, (const void*)k_finish<kFinishBlock>, kFinishBlock, 4);
   if (!gr_cache) gr_cache = grid_for(g->device, (const void*)k_resolve, kResolveBlock, 1);
+  if (!gp_cache) gp_cache = grid_for(g->device, (const void*)k_pull, kPullBlock, 1);
+  const int gp = gp_cache;
+  const int64_t n_active = c.relabeled ? c.n_active : c.n;
   const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache;
   const int gm = g->opt.grid_blocks > 0 ? std::min(g->opt.grid_blocks, c.hot_slices) : c.hot_slices;
   const int gf = gf_cache;
@@ -1019,29 +1200,35 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   const unsigned long long cmask = (1ull << c.cbits) - 1;
   const bool prof = g->opt.profile > 0;
   const int probe = g->opt.cold_probe == 3 ? 0 : g->opt.cold_probe;
-  // One level: its (up to) four launches; ev_base >= 0 brackets them with
-  // events ev_base .. ev_base + 3 (claim expand, mark expand, finish+resolve).
+  // One level: its launches; ev_base >= 0 brackets them with events
+  // ev_base .. ev_base + 4 (claim expand + hot bits | mark expand | pull |
+  // finish + resolve).
   auto enqueue_level = [&](hipStream_t st, int64_t ev_base) -> int {
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base], st));
     k_expand<kExpandBlock><<<ge, kExpandBlock, 0, st>>>(koff, kcol, c.vis, d_parent, d_level,
                                                         c.mark, q, c.jstart, c.njstart, c.zq,
                                                         c.state, c.cbits, mp, kinv);
-    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 1], st));
     if (mp.symmetric)
+      k_prev_bits<<<(c.hot_words + 255) / 256, 256, 0, st>>>(c.mark, c.state, c.cbits, mp,
+                                                             c.hot_words, c.prev_bits);
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 1], st));
+    if (mp.symmetric) {
       mark_expand_launch(gm, st, kcol, c.vis, c.mark, q, c.jstart, c.njstart, c.state, c.cbits,
                          mp, c.hot_words, c.hot_new, c.n, probe);
+    }
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 2], st));
+    if (mp.symmetric && mp.pull_alpha > 0)
+      k_pull<<<gp, kPullBlock, 0, st>>>(koff, kcol, c.vis, d_parent, d_level, c.mark, c.state,
+                                        mp, kinv, c.hot_words, c.prev_bits, n_active);
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
     k_finish<kFinishBlock><<<gf, kFinishBlock, 0, st>>>(koff, c.vis, c.mark, q, c.jstart,
                                                         c.njstart, c.zq, c.state, c.cbits, c.n,
                                                         c.nwords, mp, c.hot_words, c.hot_new,
                                                         gm);
-    if (mp.symmetric) {
-      k_prev_bits<<<(c.hot_words + 255) / 256, 256, 0, st>>>(c.mark, c.state, c.cbits, mp,
-                                                             c.hot_words, c.prev_bits);
+    if (mp.symmetric)
       k_resolve<<<gr, kResolveBlock, 0, st>>>(kcol, d_parent, d_level, c.mark, q, c.state,
                                               c.cbits, mp, kinv, c.hot_words, c.prev_bits);
-    }
-    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 4], st));
     return BFS_OK;
   };
   int64_t k = 0;
@@ -1060,6 +1247,8 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     key.grids[1] = gm;
     key.grids[2] = gf;
     key.grids[3] = gr;
+    key.mp_alpha = mp.pull_alpha;
+    key.pad = 0;
     if (!c.gexec || std::memcmp(&key, &c.gkey, sizeof(key)) != 0) {
       if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
       c.gexec = nullptr;
@@ -1101,14 +1290,14 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     for (;;) {
       for (int b = 0; b < batch; ++b) {
         if (prof) {
-          const size_t need = 4 * (size_t)(k + 1) + 2;
+          const size_t need = 5 * (size_t)(k + 1) + 2;
           while (g->ev.size() < need) {
             hipEvent_t ev;
             BFS_HIP(hipEventCreate(&ev));
             g->ev.push_back(ev);
           }
         }
-        const int rc = enqueue_level(s, prof ? 2 + 4 * k : -1);
+        const int rc = enqueue_level(s, prof ? 2 + 5 * k : -1);
         if (rc != BFS_OK) return rc;
         ++k;
       }
@@ -1145,16 +1334,21 @@ int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st) {
   st->frontier_total = (int64_t)h.frontier_total;
   st->expand_launches = g->expand_launches;
   st->mark_levels = h.mark_levels;
+  st->pull_levels = h.pull_levels;
+  st->pull_edges = (int64_t)h.pull_edges;
   if (g->profiled == 1) {
-    double sum = 0.0, msum = 0.0;
+    double sum = 0.0, msum = 0.0, psum = 0.0;
     for (int k = 0; k < g->expand_launches; ++k) {
-      float ms = 0.f, mm = 0.f;
-      BFS_HIP(hipEventElapsedTime(&ms, g->ev[2 + 4 * k], g->ev[4 + 4 * k]));
-      BFS_HIP(hipEventElapsedTime(&mm, g->ev[3 + 4 * k], g->ev[4 + 4 * k]));
+      float ms = 0.f, mm = 0.f, pm = 0.f;
+      BFS_HIP(hipEventElapsedTime(&ms, g->ev[2 + 5 * k], g->ev[5 + 5 * k]));
+      BFS_HIP(hipEventElapsedTime(&mm, g->ev[3 + 5 * k], g->ev[4 + 5 * k]));
+      BFS_HIP(hipEventElapsedTime(&pm, g->ev[4 + 5 * k], g->ev[5 + 5 * k]));
       sum += ms;
       msum += mm;
+      psum += pm;
     }
     st->mark_ms = msum;
+    st->pull_ms = psum;
     st->expand_ms = sum;
   }
   if (g->profiled) {
@@ -1170,9 +1364,12 @@ int csr_level_info(bfs_graph* g, bfs_level_info_t* out, int32_t capacity, int32_
   const int n = std::min<int>(std::min(capacity, g->expand_launches), kLevelHist - 1);
   std::vector<unsigned long long> hist((size_t)n + 1);
   std::vector<int32_t> hmark((size_t)n + 1);
+  std::vector<unsigned long long> hpc((size_t)n + 1), hpe((size_t)n + 1);
   BFS_HIP(hipMemcpy(hist.data(), g->csr.state->hist, hist.size() * 8, hipMemcpyDeviceToHost));
   BFS_HIP(hipMemcpy(hmark.data(), g->csr.state->hist_mark, hmark.size() * 4,
                     hipMemcpyDeviceToHost));
+  BFS_HIP(hipMemcpy(hpc.data(), g->csr.state->hist_pc, hpc.size() * 8, hipMemcpyDeviceToHost));
+  BFS_HIP(hipMemcpy(hpe.data(), g->csr.state->hist_pe, hpe.size() * 8, hipMemcpyDeviceToHost));
   const unsigned long long cmask = (1ull << g->csr.cbits) - 1;
   for (int i = 0; i < n; ++i) {
     const int k = i + 1;
@@ -1181,14 +1378,18 @@ int csr_level_info(bfs_graph* g, bfs_level_info_t* out, int32_t capacity, int32_
     L.mark = hmark[(size_t)k];
     L.frontier = (int64_t)(hist[(size_t)k] & cmask);
     L.edges = (int64_t)(hist[(size_t)k] >> g->csr.cbits);
-    float a = 0.f, m = 0.f, b = 0.f;
+    L.pull_candidates = (int64_t)hpc[(size_t)k];
+    L.pull_edges = (int64_t)hpe[(size_t)k];
+    float a = 0.f, m = 0.f, pl = 0.f, b = 0.f;
     if (g->profiled == 1) {   // per-level events exist (not in graph mode)
-      BFS_HIP(hipEventElapsedTime(&a, g->ev[2 + 4 * i], g->ev[4 + 4 * i]));
-      BFS_HIP(hipEventElapsedTime(&m, g->ev[3 + 4 * i], g->ev[4 + 4 * i]));
-      BFS_HIP(hipEventElapsedTime(&b, g->ev[4 + 4 * i], g->ev[5 + 4 * i]));
+      BFS_HIP(hipEventElapsedTime(&a, g->ev[2 + 5 * i], g->ev[5 + 5 * i]));
+      BFS_HIP(hipEventElapsedTime(&m, g->ev[3 + 5 * i], g->ev[4 + 5 * i]));
+      BFS_HIP(hipEventElapsedTime(&pl, g->ev[4 + 5 * i], g->ev[5 + 5 * i]));
+      BFS_HIP(hipEventElapsedTime(&b, g->ev[5 + 5 * i], g->ev[6 + 5 * i]));
     }
     L.expand_ms = a;
     L.mark_ms = m;
+    L.pull_ms = pl;
     L.finish_ms = b;
   }
   *count = g->expand_launches;

@@ -51,10 +51,16 @@ struct LevelState {
   unsigned int zcnt[3];
   int32_t error;
   int32_t mark_levels;   // levels resolved by mark-and-resolve
+  int32_t pull;          // the current level computes its product by rows (pull)
+  int32_t pull_levels;   // levels computed by rows
   int32_t pad;
+  unsigned long long pull_edges;   // adjacencies examined by the pull levels
   // input frontier counter of each level (profiling; levels < kLevelHist)
   unsigned long long hist[4096];
-  int32_t hist_mark[4096];
+  int32_t hist_mark[4096];   // 0 claim, 1 mark-and-resolve, 2 pull
+  // pull levels: vertices that searched, adjacencies they examined
+  unsigned long long hist_pc[4096];
+  unsigned long long hist_pe[4096];
 };
 constexpr int kLevelHist = 4096;
 
@@ -65,6 +71,7 @@ struct GraphKey {
   long long mp_edges, mp_vertices;
   int mp_sym, probe;
   int grids[4];
+  int mp_alpha, pad;
 };
 
 struct CsrDev {
@@ -98,6 +105,8 @@ struct CsrDev {
   // rank of the vertex by descending degree; each row keeps its adjacencies
   // in ascending original id, mapped to new ids
   int relabeled = 0;
+  int64_t n_active = 0;          // every vertex of positive degree has a level-kernel id
+                                 // below this (n unless relabelled by degree)
   int64_t* roff = nullptr;       // n + 1, rows in new order
   int32_t* rcol = nullptr;       // nnz, new ids
   int32_t* rank = nullptr;       // original id -> new id

@@ -41,6 +41,11 @@ struct MarkPolicy {
   int symmetric;
   long long min_edges;
   long long min_vertices;
+  // a mark level pulls (computes its product by rows) when
+  // pull_alpha * frontier adjacencies >= adjacencies not yet visited;
+  // 0 = never
+  long long nnz;
+  int pull_alpha;
 };
 
 __device__ __forceinline__ bool mark_level(unsigned long long cin, int cbits,

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kMarkBlock) void k_expand_mark(
   const unsigned long long cin = st->ctr[kin % 3];
   const int64_t F = (int64_t)(cin & cmask);
   const int64_t T = (int64_t)(cin >> cbits);
-  if (F == 0 || !mark_level(cin, cbits, mp)) return;
+  if (F == 0 || !mark_level(cin, cbits, mp) || st->pull) return;   // push levels only
   const int tid = threadIdx.x;
   for (int i = tid; i < hw; i += kMarkBlock) s_hot[i] = vis[i];
   __syncthreads();

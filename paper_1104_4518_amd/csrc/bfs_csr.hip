@@ -5,10 +5,14 @@
 // newly reached vertex takes the smallest frontier id among its neighbours
 // as its parent.
 //
-// One level k is up to four launches, all reading the level number and the
-// frontier counters from device memory (consecutive levels have identical
-// arguments; a launch whose level does not concern it exits at once, so the
-// host enqueues several levels between reads of the frontier size):
+// One level k is a fixed sequence of launches, all reading the level number
+// and the frontier counters from device memory (consecutive levels have
+// identical arguments; a launch whose level does not concern it exits at
+// once, so the host enqueues several levels between reads of the frontier
+// size). The level kernels work in the ids of the CSR they read (degree
+// order when relabelled) and record a reached vertex as one word,
+// (level << 32) | parent's caller id; k_out writes the caller's arrays from
+// those words after the last level.
 //
 //   expand(k)  streams the adjacencies of frontier k-1 in edge-balanced
 //              tiles (an exclusive degree prefix of the frontier maps every
@@ -16,24 +20,29 @@
 //              and workgroups) and tests the visited bitmap, then claims the
 //              unvisited targets in one of two ways, chosen per level from
 //              the frontier's size:
-//                claim  (k_expand) atomicMin on parent[]; the thread whose
-//                       atomic turned parent from -1 into a frontier id
+//                claim  (k_expand) 64-bit atomicMin on the target's word;
+//                       the thread whose atomic replaced the all-ones word
 //                       appends the vertex to the next frontier (small
 //                       frontiers: few atomics);
 //                mark   (k_expand_mark, bfs_mark.hip) the target is recorded as touched,
 //                       with no atomics per edge: in an LDS copy of the hot
 //                       prefix of the visited bitmap, or by a byte store
 //                       (large frontiers, symmetric graphs).
+//   pull(k)    instead of the mark expand, once the frontier's adjacencies
+//              outweigh those of the unvisited vertices: every unvisited
+//              vertex searches its own adjacency list for a vertex of
+//              frontier k-1 (the product evaluated by rows) and is marked
+//              touched with its parent found.
 //   finish(k)  claim levels: sets the visited bits of the new frontier.
 //              mark levels: collects the touched vertices one 32-vertex word
 //              per thread, appends them to the next frontier, sets their
 //              visited bits and gives them the level's tag.
-//   resolve(k) mark levels: gives each vertex of the new frontier its level
-//              and its parent, the first neighbour one level up in its
-//              ascending adjacency list (for an undirected graph that is the
-//              minimum frontier id adjacent to it).
+//   resolve(k) push mark levels: gives each vertex of the new frontier its
+//              level and its parent, the first neighbour one level up in
+//              its ascending adjacency list (for an undirected graph that is
+//              the minimum frontier id adjacent to it).
 //
-// Both ways give the same parents: the unique minimum-id neighbour one
+// All ways give the same parents: the unique minimum-id neighbour one
 // level up. Appends to the next frontier are aggregated per workgroup into
 // one atomic on a packed (edge total, vertex count) counter, which also
 // yields the degree prefix the next level needs to split its work by edges.
@@ -48,14 +57,16 @@
 namespace bfsi {
 namespace {
 
-__global__ void k_init(int64_t n, int32_t* __restrict__ parent, int32_t* __restrict__ level,
+// The level kernels record a reached vertex as one word in their own ids,
+// (level << 32) | parent's caller id, all ones while unreached (the claim
+// path's 64-bit atomicMin then orders claims by level, then by parent id);
+// k_out writes the caller's parent and level arrays from it at the end.
+// Vertices of degree 0 past n_active are only ever reached as the root.
+__global__ void k_init(int64_t n_active, unsigned long long* __restrict__ rpl,
                        uint32_t* __restrict__ vis, int64_t nwords, uint4* __restrict__ mark) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = i; v < n; v += stride) {
-    parent[v] = -1;
-    if (level) level[v] = -1;
-  }
+  for (int64_t v = i; v < n_active; v += stride) rpl[v] = ~0ull;
   for (int64_t w = i; w < nwords; w += stride) {
     vis[w] = 0u;
     if (mark) {
@@ -65,14 +76,13 @@ __global__ void k_init(int64_t n, int32_t* __restrict__ parent, int32_t* __restr
   }
 }
 
-__global__ void k_seed(const int64_t* __restrict__ off, int32_t root, int32_t* parent,
-                       int32_t* level, uint32_t* vis, uint8_t* mark, Queues q, int32_t* jstart,
+__global__ void k_seed(const int64_t* __restrict__ off, int32_t root, unsigned long long* rpl,
+                       uint32_t* vis, uint8_t* mark, Queues q, int32_t* jstart,
                        LevelState* st, int cbits, const int32_t* __restrict__ rank) {
-  // outputs are indexed by the caller's ids; everything else by the ids of
+  // parents are the caller's ids; everything else is indexed by the ids of
   // the CSR the level kernels read (degree order when relabelled)
-  parent[root] = root;
-  if (level) level[root] = 0;
   const int32_t r = rank ? rank[root] : root;
+  rpl[r] = (unsigned long long)(uint32_t)root;   // level 0
   vis[r >> 5] |= 1u << (r & 31);
   if (mark) mark[r] = level_tag(0);
   const int64_t o = off[r];
@@ -159,7 +169,7 @@ __device__ __forceinline__ void map_tiles(int32_t* __restrict__ jstart, long lon
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_expand(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col,
-    const uint32_t* __restrict__ vis, int32_t* __restrict__ parent, int32_t* __restrict__ level,
+    const uint32_t* __restrict__ vis, unsigned long long* __restrict__ rpl,
     uint8_t* __restrict__ mark, Queues q, int32_t* __restrict__ jstart_base, int64_t njs,
     int32_t* __restrict__ zq, LevelState* st, int cbits, MarkPolicy mp,
     const int32_t* __restrict__ inv) {
@@ -238,7 +248,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     for (int i = 0; i < ITEMS; ++i) {
       const int64_t e = e0 + (int64_t)i * BLOCK + tid;
       bool own = false;
-      int32_t v = 0, vout = 0;
+      int32_t v = 0;
       if (e < e1) {
         // row of edge e: last r with s_qe[r] <= e (rows are non-empty)
         int lo = 0, hi = R - 1;
@@ -251,17 +261,15 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
         const uint32_t u = (uint32_t)(inv ? inv[uj] : uj);   // caller's id of the frontier vertex
         v = col[qo_in[j] + (e - s_qe[lo])];
         if (!((vis[v >> 5] >> (v & 31)) & 1u)) {
-          vout = inv ? inv[v] : v;
-          const uint32_t cur = reinterpret_cast<const uint32_t*>(parent)[vout];
-          if (cur > u) {
-            const uint32_t old = atomicMin(reinterpret_cast<uint32_t*>(parent) + vout, u);
-            own = (old == 0xFFFFFFFFu);
+          const unsigned long long key = ((unsigned long long)k << 32) | u;
+          if (rpl[v] > key) {
+            const unsigned long long old = atomicMin(rpl + v, key);
+            own = (old == ~0ull);
           }
         }
       }
       int32_t deg = 0;
       if (own) {
-        if (level) level[vout] = k;
         if (mp.symmetric) mark[v] = level_tag(k);
         deg = (int32_t)(off[v + 1] - off[v]);
         ++my_reached;
@@ -702,7 +710,7 @@ __device__ __forceinline__ void first_up(const int32_t* __restrict__ col,
 }
 
 __global__ __launch_bounds__(kResolveBlock) void k_resolve(
-    const int32_t* __restrict__ col, int32_t* __restrict__ parent, int32_t* __restrict__ level,
+    const int32_t* __restrict__ col, unsigned long long* __restrict__ rpl,
     const uint8_t* __restrict__ mark, Queues q, const LevelState* __restrict__ st, int cbits,
     MarkPolicy mp, const int32_t* __restrict__ inv, int hw,
     const uint32_t* __restrict__ prev_bits) {
@@ -750,9 +758,8 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
 #pragma unroll
     for (int t = 0; t < kResolveRV; ++t) {
       if (v[t] < 0) continue;
-      const int32_t vo = inv ? inv[v[t]] : v[t];
-      parent[vo] = (inv && p[t] >= 0) ? inv[p[t]] : p[t];
-      if (level) level[vo] = k;
+      const int32_t pc = (inv && p[t] >= 0) ? inv[p[t]] : p[t];
+      rpl[v[t]] = ((unsigned long long)k << 32) | (uint32_t)pc;
     }
   }
 }
@@ -773,7 +780,7 @@ constexpr int kPullRV = 2;
 
 __global__ __launch_bounds__(kPullBlock) void k_pull(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col,
-    const uint32_t* __restrict__ vis, int32_t* __restrict__ parent, int32_t* __restrict__ level,
+    const uint32_t* __restrict__ vis, unsigned long long* __restrict__ rpl,
     uint8_t* __restrict__ mark, LevelState* st, MarkPolicy mp, const int32_t* __restrict__ inv,
     int hw, const uint32_t* __restrict__ prev_bits, int64_t n_active) {
   constexpr int WAVES = kPullBlock / 64;
@@ -845,9 +852,8 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
         my_cand += end[t] > o[t];   // vertices of degree 0 have nothing to search
         my_edges += (unsigned long long)((p[t] >= 0 ? at[t] + 1 : end[t]) - o[t]);
         if (p[t] < 0) continue;
-        const int32_t vo = inv ? inv[v[t]] : v[t];
-        parent[vo] = inv ? inv[p[t]] : p[t];
-        if (level) level[vo] = k;
+        const int32_t pc = inv ? inv[p[t]] : p[t];
+        rpl[v[t]] = ((unsigned long long)k << 32) | (uint32_t)pc;
         mark[v[t]] = 1;
       }
     }
@@ -876,6 +882,21 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
       atomicAdd(&st->hist_pc[k], a);
       atomicAdd(&st->hist_pe[k], b);
     }
+  }
+}
+
+// The caller's arrays from the level kernels' words: caller id x reads the
+// word of its level-kernel id (a gather: the writes stay coalesced); ids of
+// degree 0 past n_active other than the root were never reached.
+__global__ void k_out(int64_t n, const int32_t* __restrict__ rank, int64_t n_active,
+                      int32_t root, const unsigned long long* __restrict__ rpl,
+                      int32_t* __restrict__ parent, int32_t* __restrict__ level) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += stride) {
+    const int64_t r = rank ? rank[x] : x;
+    const unsigned long long w = (r < n_active || x == root) ? rpl[r] : ~0ull;
+    parent[x] = (int32_t)(uint32_t)w;
+    if (level) level[x] = (int32_t)(uint32_t)(w >> 32);
   }
 }
 
@@ -984,6 +1005,7 @@ int csr_alloc_workspace(bfs_graph* g) {
   c.nwords = (c.n + 31) / 32;
   c.njstart = c.nnz / kTileJ + 2;
   BFS_HIP(hipMalloc(&c.vis, (size_t)std::max<int64_t>(c.nwords, 1) * 4));
+  BFS_HIP(hipMalloc(&c.rpl, (size_t)std::max<int64_t>(c.n, 1) * 8));
   for (int b = 0; b < 2; ++b) {
     BFS_HIP(hipMalloc(&c.qv[b], (size_t)c.n * 4));
     BFS_HIP(hipMalloc(&c.qo[b], (size_t)c.n * 8));
@@ -1005,7 +1027,7 @@ int csr_alloc_workspace(bfs_graph* g) {
     g->device_bytes += (int64_t)c.hot_words * 4;
     g->device_bytes += (int64_t)c.hot_slices * c.hot_words * 4;
   }
-  g->device_bytes += std::max<int64_t>(c.nwords, 1) * 4 + c.n * 44 + c.njstart * 8 +
+  g->device_bytes += std::max<int64_t>(c.nwords, 1) * 4 + c.n * 52 + c.njstart * 8 +
                      (int64_t)sizeof(LevelState);
   return BFS_OK;
 }
@@ -1015,6 +1037,7 @@ void csr_free(bfs_graph* g) {
   (void)hipFree(c.off);
   (void)hipFree(c.col);
   (void)hipFree(c.vis);
+  (void)hipFree(c.rpl);
   for (int b = 0; b < 2; ++b) {
     (void)hipFree(c.qv[b]);
     (void)hipFree(c.qo[b]);
@@ -1115,9 +1138,14 @@ int csr_relabel(bfs_graph* g, const int64_t* host_off, hipStream_t s) {
   BFS_HIP(hipGetLastError());
   BFS_HIP(hipStreamSynchronize(s));
   c.relabeled = 1;
-  // degree-descending order: the vertices of positive degree come first
-  c.n_active = 0;
-  while (c.n_active < n && roff[(size_t)c.n_active + 1] > roff[(size_t)c.n_active]) ++c.n_active;
+  // degree-descending order: the vertices of positive degree come first;
+  // only in a symmetric graph are the others unreachable (a directed graph
+  // reaches vertices of out-degree 0)
+  c.n_active = n;
+  if (c.symmetric) {
+    c.n_active = 0;
+    while (c.n_active < n && roff[(size_t)c.n_active + 1] > roff[(size_t)c.n_active]) ++c.n_active;
+  }
   g->device_bytes += (n + 1) * 8 + std::max<int64_t>(c.nnz, 1) * 4 + n * 8;
   return BFS_OK;
 }
@@ -1170,14 +1198,16 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     }
     BFS_HIP(hipEventRecord(g->ev[0], s));
   }
-  k_init<<<std::max(igrid, 1), ib, 0, s>>>(c.n, d_parent, d_level, c.vis, c.nwords,
+  const int64_t n_active = c.relabeled ? c.n_active : c.n;
+  k_init<<<std::max(igrid, 1), ib, 0, s>>>(n_active, c.rpl, c.vis, c.nwords,
                                            reinterpret_cast<uint4*>(c.mark));
   // the level kernels read the degree-ordered copy when there is one
   const int64_t* koff = c.relabeled ? c.roff : c.off;
   const int32_t* kcol = c.relabeled ? c.rcol : c.col;
   const int32_t* kinv = c.relabeled ? c.inv : nullptr;
-  k_seed<<<1, 1, 0, s>>>(koff, root, d_parent, d_level, c.vis, mp.symmetric ? c.mark : nullptr,
-                         q, c.jstart, c.state, c.cbits, c.relabeled ? c.rank : nullptr);
+  const int32_t* krank = c.relabeled ? c.rank : nullptr;
+  k_seed<<<1, 1, 0, s>>>(koff, root, c.rpl, c.vis, mp.symmetric ? c.mark : nullptr,
+                         q, c.jstart, c.state, c.cbits, krank);
 
   // launch shapes: the claim expand and finish fill the chip with 256-thread
   // workgroups; the mark expand runs one 1024-thread workgroup per CU (its
@@ -1189,7 +1219,6 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   if (!gr_cache) gr_cache = grid_for(g->device, (const void*)k_resolve, kResolveBlock, 1);
   if (!gp_cache) gp_cache = grid_for(g->device, (const void*)k_pull, kPullBlock, 1);
   const int gp = gp_cache;
-  const int64_t n_active = c.relabeled ? c.n_active : c.n;
   const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache;
   const int gm = g->opt.grid_blocks > 0 ? std::min(g->opt.grid_blocks, c.hot_slices) : c.hot_slices;
   const int gf = gf_cache;
@@ -1205,7 +1234,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   // finish + resolve).
   auto enqueue_level = [&](hipStream_t st, int64_t ev_base) -> int {
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base], st));
-    k_expand<kExpandBlock><<<ge, kExpandBlock, 0, st>>>(koff, kcol, c.vis, d_parent, d_level,
+    k_expand<kExpandBlock><<<ge, kExpandBlock, 0, st>>>(koff, kcol, c.vis, c.rpl,
                                                         c.mark, q, c.jstart, c.njstart, c.zq,
                                                         c.state, c.cbits, mp, kinv);
     if (mp.symmetric)
@@ -1218,7 +1247,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     }
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 2], st));
     if (mp.symmetric && mp.pull_alpha > 0)
-      k_pull<<<gp, kPullBlock, 0, st>>>(koff, kcol, c.vis, d_parent, d_level, c.mark, c.state,
+      k_pull<<<gp, kPullBlock, 0, st>>>(koff, kcol, c.vis, c.rpl, c.mark, c.state,
                                         mp, kinv, c.hot_words, c.prev_bits, n_active);
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
     k_finish<kFinishBlock><<<gf, kFinishBlock, 0, st>>>(koff, c.vis, c.mark, q, c.jstart,
@@ -1226,7 +1255,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
                                                         c.nwords, mp, c.hot_words, c.hot_new,
                                                         gm);
     if (mp.symmetric)
-      k_resolve<<<gr, kResolveBlock, 0, st>>>(kcol, d_parent, d_level, c.mark, q, c.state,
+      k_resolve<<<gr, kResolveBlock, 0, st>>>(kcol, c.rpl, c.mark, q, c.state,
                                               c.cbits, mp, kinv, c.hot_words, c.prev_bits);
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 4], st));
     return BFS_OK;
@@ -1237,8 +1266,6 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     // launch shapes) and replayed until a level finds an empty frontier;
     // replays between host checks double up to 8.
     GraphKey key{};
-    key.parent = d_parent;
-    key.level = d_level;
     key.mp_sym = mp.symmetric;
     key.mp_edges = mp.min_edges;
     key.mp_vertices = mp.min_vertices;
@@ -1310,6 +1337,8 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     }
   }
   g->expand_launches = (int)k;
+  k_out<<<std::max(igrid, 1), ib, 0, s>>>(c.n, krank, n_active, root, c.rpl, d_parent, d_level);
+  BFS_HIP(hipGetLastError());
   if (prof) BFS_HIP(hipEventRecord(g->ev[1], s));
   if (host_parent)
     BFS_HIP(hipMemcpyAsync(parent, d_parent, (size_t)c.n * 4, hipMemcpyDeviceToHost, s));

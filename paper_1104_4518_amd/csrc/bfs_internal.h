@@ -66,8 +66,6 @@ constexpr int kLevelHist = 4096;
 
 // What a captured level graph depends on besides the handle's own buffers.
 struct GraphKey {
-  const void* parent;
-  const void* level;
   long long mp_edges, mp_vertices;
   int mp_sym, probe;
   int grids[4];
@@ -81,6 +79,7 @@ struct CsrDev {
   int32_t* col = nullptr;        // nnz
   // workspace
   uint32_t* vis = nullptr;       // visited bitmap, ceil(n / 32) words
+  unsigned long long* rpl = nullptr;   // n: (level << 32) | parent per level-kernel id
   int64_t nwords = 0;
   int32_t* qv[2] = {nullptr, nullptr};   // frontier vertex ids
   int64_t* qo[2] = {nullptr, nullptr};   // row start off[v] of each entry
@@ -105,8 +104,8 @@ struct CsrDev {
   // rank of the vertex by descending degree; each row keeps its adjacencies
   // in ascending original id, mapped to new ids
   int relabeled = 0;
-  int64_t n_active = 0;          // every vertex of positive degree has a level-kernel id
-                                 // below this (n unless relabelled by degree)
+  int64_t n_active = 0;          // symmetric relabelled graphs: every vertex of positive
+                                 // degree has a level-kernel id below this (else n)
   int64_t* roff = nullptr;       // n + 1, rows in new order
   int32_t* rcol = nullptr;       // nnz, new ids
   int32_t* rank = nullptr;       // original id -> new id

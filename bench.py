@@ -8,11 +8,13 @@ steps of per-root TEPS, with TEPS = (undirected edges of the searched
 component) / (BFS time), in GTEPS.
 
 The JSON line also carries:
-  roofline      the mark-and-resolve expand kernel k_expand_mark (the dominant
-                kernel on R-MAT): algorithmic bytes per launch / average
+  roofline      the dominant level kernel on R-MAT, k_pull (the levels whose
+                product is computed by rows) or k_expand_mark (push levels),
+                whichever took longer: algorithmic bytes per launch / average
                 launch duration, both from HIP events recorded around every
                 launch of it on its stream (one launch per enqueued level;
-                claim levels' launches exit at once and count too)
+                launches on levels of the other kinds exit at once and count
+                too)
   cpu_baseline  the CPU oracle (serial C) timed on a bounded sample of roots
   bfs_roofline_frac  whole-BFS algorithmic bytes / BFS time, per root
   spmspv        the 2D share (2^26 x 2^26 DCSC, 2^24 uniform nonzeros): 200
@@ -50,10 +52,26 @@ def mark_expand_bytes(levels) -> float:
     touch mark)."""
     total = 0.0
     for i, L in enumerate(levels):
-        if not L["mark"]:
+        if L["mark"] != 1:
             continue
         new = levels[i + 1]["frontier"] if i + 1 < len(levels) else 0
         total += 4.125 * L["edges"] + 16.0 * L["frontier"] + 1.0 * new
+    return total
+
+
+def pull_bytes(levels, n_active: int) -> float:
+    """Algorithmic bytes of the pull launches of one BFS, from its per-level
+    record: per pull level the visited bits of the n_active vertices of
+    positive degree; per searching vertex 8 B (its adjacency start); per
+    examined adjacency 4 B + 1/8 B (the adjacency and the neighbour's
+    frontier bit); per vertex found 13 B (its packed level and parent word,
+    its touch mark, the parent's caller id)."""
+    total = 0.0
+    for i, L in enumerate(levels):
+        if L["mark"] != 2:
+            continue
+        new = levels[i + 1]["frontier"] if i + 1 < len(levels) else 0
+        total += n_active / 8.0 + 8.0 * L["pull_candidates"] + 4.125 * L["pull_edges"] + 13.0 * new
     return total
 
 
@@ -62,13 +80,16 @@ def bfs_bytes(n: int, edges: int, reached: int) -> float:
     return 4.125 * edges + 24.0 * reached + 8.0 * n + n / 4.0
 
 
-def profiled_traffic(workload: str):
-    """HBM bytes per mark expand launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+KERNEL_SOURCE = {"k_expand_mark": "bfs_mark.hip", "k_pull": "bfs_csr.hip"}
+
+
+def profiled_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of the kernel from the committed rocprofv3
+    counter summary, or None when its source changed since it was taken."""
     import hashlib
     import re
-    prof = os.path.join(ROOT, "profiles", f"k_expand_mark_{workload}.md")
-    src = os.path.join(ROOT, "paper_1104_4518_amd", "csrc", "bfs_mark.hip")
+    prof = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    src = os.path.join(ROOT, "paper_1104_4518_amd", "csrc", KERNEL_SOURCE[kernel])
     try:
         text = open(prof).read()
         want = re.search(r"source_sha256_16:\s*([0-9a-f]+)", text).group(1)
@@ -125,7 +146,7 @@ def bfs_leg(args, torch, graphgen, B):
     G.tune(args.tune_cache)   # launch shapes and mark-level floor, measured on this graph (untimed)
     opt = G.get_options()
     tuned = {"grid_blocks": opt.grid_blocks, "batch_levels": opt.batch_levels,
-             "claim_min_frontier": opt.claim_min_frontier}
+             "claim_min_frontier": opt.claim_min_frontier, "pull_alpha": opt.pull_alpha}
     log(f"tuned in {time.time() - t_tune:.1f}s: {tuned}")
     G.set_options(profile=1)
     parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
@@ -158,8 +179,14 @@ def bfs_leg(args, torch, graphgen, B):
     giant_size = max(st.reached for st in stats)
     giant = [i for i, st in enumerate(stats) if st.reached == giant_size]
     per_root_gteps, per_root_frac = [], []
-    exp_bytes = exp_ms = 0.0
-    exp_launches = 0
+    import numpy as np
+    deg = np.diff(np.asarray(g.off))
+    # the pull scans the vertices of positive degree of the degree-ordered copy
+    # (graphs of 2^20 vertices and more), else all vertices
+    n_active = int((deg > 0).sum()) if g.n >= (1 << 20) else g.n
+    kb = {"k_expand_mark": 0.0, "k_pull": 0.0}
+    kms = {"k_expand_mark": 0.0, "k_pull": 0.0}
+    launches = 0
     for i, st in enumerate(stats):
         ms = starts[i].elapsed_time(ends[i])
         if st.reached == giant_size:
@@ -167,13 +194,18 @@ def bfs_leg(args, torch, graphgen, B):
             per_root_gteps.append(m_r / (ms * 1e-3) / 1e9)
             per_root_frac.append(bfs_bytes(g.n, st.edges_traversed, st.reached) /
                                  (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
-        exp_bytes += mark_expand_bytes(levels[i])
-        exp_ms += st.mark_ms
-        exp_launches += st.expand_launches   # one mark expand launch per enqueued level
+        kb["k_expand_mark"] += mark_expand_bytes(levels[i])
+        kb["k_pull"] += pull_bytes(levels[i], n_active)
+        kms["k_expand_mark"] += st.mark_ms
+        kms["k_pull"] += st.pull_ms
+        launches += st.expand_launches   # one launch of each per enqueued level
     value = harmonic(per_root_gteps)
+    kern = max(kms, key=lambda k: kms[k])
+    exp_bytes, exp_ms, exp_launches = kb[kern], kms[kern], launches
     achieved = exp_bytes / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else 0.0
-    log(f"timed {args.steps} roots in {wall:.3f}s wall; {value:.2f} GTEPS; mark expand "
-        f"{exp_launches} launches avg {exp_ms / max(exp_launches, 1) * 1e3:.1f} us")
+    log(f"timed {args.steps} roots in {wall:.3f}s wall; {value:.2f} GTEPS; {kern} "
+        f"{exp_launches} launches avg {exp_ms / max(exp_launches, 1) * 1e3:.1f} us; "
+        f"k_expand_mark {kms['k_expand_mark']:.3f} ms, k_pull {kms['k_pull']:.3f} ms in total")
     res = {
         "value": value,
         "wall": wall,
@@ -190,12 +222,12 @@ def bfs_leg(args, torch, graphgen, B):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_expand_mark",
+            "kernel": kern,
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": profiled_traffic(args.workload),
+            "traffic": profiled_traffic(kern, args.workload),
             "launches": exp_launches,
             "avg_launch_us": round(exp_ms / max(exp_launches, 1) * 1e3, 3),
             "bytes_per_launch": round(exp_bytes / max(exp_launches, 1), 1),

@@ -108,6 +108,9 @@ __global__ void k_seed(const int64_t* __restrict__ off, int32_t root, unsigned l
   st->pull = 0;
   st->pull_levels = 0;
   st->pull_edges = 0ull;
+  st->pull_found = 0ull;
+  st->pull_found_edges = 0ull;
+  st->qskip = 0;
 }
 
 // Block-wide exclusive scan of (count, degree sum) pairs; returns the
@@ -197,18 +200,13 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
       st->frontier_total += (unsigned long long)F;
       if (mark_level(cin, cbits, mp)) {
         st->mark_levels += 1;
-        // direction of the product: by rows once the frontier's adjacencies
-        // outweigh (by pull_alpha) those of the vertices still unvisited,
-        // which the pull would examine at most
-        const unsigned long long seen = st->edges;
-        const unsigned long long rest =
-            (unsigned long long)mp.nnz > seen ? (unsigned long long)mp.nnz - seen : 0ull;
-        pull = mp.pull_alpha > 0 &&
-               (unsigned long long)T * (unsigned long long)mp.pull_alpha >= rest;
+        pull = pull_level(cin, cbits, st->edges, mp);
         st->pull_levels += pull;
       }
     }
     st->pull = pull;
+    st->pull_found = 0ull;
+    st->pull_found_edges = 0ull;
     if (k < kLevelHist) {
       st->hist[k] = cin;
       st->hist_mark[k] = pull ? 2 : (mark_level(cin, cbits, mp) ? 1 : 0);
@@ -399,6 +397,45 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   unsigned long long* ctr_out = &st->ctr[k % 3];
   uint4* __restrict__ mark4 = reinterpret_cast<uint4*>(mark);
   const uint32_t tcur = level_tag(k);
+  // A pull level whose successor pulls too builds no queue (nothing reads
+  // it): its own count of the vertices it found and their adjacencies is
+  // the next level's input counter, and the successor's direction follows
+  // from it as that level's expand will decide it.
+  if (st->pull) {
+    const unsigned long long pf = st->pull_found, pe = st->pull_found_edges;
+    const unsigned long long cnext = (pe << cbits) | pf;
+    if (pull_level(cnext, cbits, st->edges + pe, mp)) {
+      uint4* __restrict__ m4 = reinterpret_cast<uint4*>(mark);
+      for (int64_t w = blockIdx.x * (int64_t)BLOCK + tid; w < nwords; w += stride) {
+        const uint4 a = m4[2 * w], b = m4[2 * w + 1];
+        uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int byte = 0; byte < 4; ++byte)
+            if (((x[i] >> (8 * byte)) & 0xFFu) == 1u) {
+              m |= 1u << (4 * i + byte);
+              x[i] = (x[i] & ~(0xFFu << (8 * byte))) | (tcur << (8 * byte));
+            }
+        if (m) {
+          m4[2 * w] = make_uint4(x[0], x[1], x[2], x[3]);
+          m4[2 * w + 1] = make_uint4(x[4], x[5], x[6], x[7]);
+          vis[w] |= m;
+        }
+      }
+      if (blockIdx.x == 0 && tid == 0) {
+        st->ctr[k % 3] = cnext;
+        st->qskip = 1;
+        if (pf) {
+          st->reached += pf;
+          if (st->depth < k) st->depth = k;
+        }
+      }
+      return;
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) st->qskip = 0;
   // a pull level marks every vertex it reaches with a byte; the expand
   // workgroups' hot slices belong to the last push level then
   const int ns = st->pull ? 0 : nslices;
@@ -581,46 +618,46 @@ __device__ __forceinline__ bool prev_level(int32_t u, int64_t hotv, const uint32
 // s_prev below hotv) in each of the thread's RV adjacency ranges
 // [o[t], end[t]): p[t] = that neighbour and at[t] = its position, or p[t] =
 // -1 and at[t] = end[t]. Entries with v[t] < 0 have empty ranges. The RV
-// searches of a thread test their first kFirst adjacencies together, then
+// searches of a thread test their first KF adjacencies together, then
 // advance four at a time up to kSerialScan; the wave finishes the longer
 // searches together, 64 adjacencies per step, so every lane of the wave
 // must make the call.
-template <int RV>
+template <int RV, int KF>
 __device__ __forceinline__ void first_up(const int32_t* __restrict__ col,
                                          const uint8_t* __restrict__ mark,
                                          const uint32_t* s_prev, int64_t hotv, uint8_t tprev,
                                          int lane, const int32_t (&v)[RV], const int64_t (&o)[RV],
                                          const int64_t (&end)[RV], int32_t (&p)[RV],
                                          int64_t (&at)[RV]) {
-  // first kFirst adjacencies of all RV vertices together; the LDS tests of
+  // first KF adjacencies of all RV vertices together; the LDS tests of
   // hot neighbours come first, so mark bytes are read only for the cold
   // neighbours ahead of the first hot hit
-  int32_t u[RV][kFirst];
+  int32_t u[RV][KF];
 #pragma unroll
   for (int t = 0; t < RV; ++t)
 #pragma unroll
-    for (int i = 0; i < kFirst; ++i) u[t][i] = o[t] + i < end[t] ? col[o[t] + i] : -1;
+    for (int i = 0; i < KF; ++i) u[t][i] = o[t] + i < end[t] ? col[o[t] + i] : -1;
   int hh[RV];
 #pragma unroll
   for (int t = 0; t < RV; ++t) {
-    hh[t] = kFirst;
+    hh[t] = KF;
 #pragma unroll
-    for (int i = kFirst - 1; i >= 0; --i)
+    for (int i = KF - 1; i >= 0; --i)
       if (u[t][i] >= 0 && u[t][i] < hotv && ((s_prev[u[t][i] >> 5] >> (u[t][i] & 31)) & 1u))
         hh[t] = i;
   }
-  uint8_t cm[RV][kFirst];
+  uint8_t cm[RV][KF];
 #pragma unroll
   for (int t = 0; t < RV; ++t)
 #pragma unroll
-    for (int i = 0; i < kFirst; ++i)
+    for (int i = 0; i < KF; ++i)
       cm[t][i] = (i < hh[t] && u[t][i] >= hotv) ? mark[u[t][i]] : (uint8_t)0;
 #pragma unroll
   for (int t = 0; t < RV; ++t) {
-    p[t] = hh[t] < kFirst ? u[t][hh[t] < kFirst ? hh[t] : 0] : -1;
-    at[t] = hh[t] < kFirst ? o[t] + hh[t] : end[t];
+    p[t] = hh[t] < KF ? u[t][hh[t] < KF ? hh[t] : 0] : -1;
+    at[t] = hh[t] < KF ? o[t] + hh[t] : end[t];
 #pragma unroll
-    for (int i = kFirst - 1; i >= 0; --i)
+    for (int i = KF - 1; i >= 0; --i)
       if (i < hh[t] && cm[t][i] == tprev) {
         p[t] = u[t][i];
         at[t] = o[t] + i;
@@ -633,7 +670,7 @@ __device__ __forceinline__ void first_up(const int32_t* __restrict__ col,
     int64_t e[RV], lim[RV];
 #pragma unroll
     for (int t = 0; t < RV; ++t) {
-      e[t] = o[t] + kFirst;
+      e[t] = o[t] + KF;
       lim[t] = min(end[t], o[t] + (int64_t)kSerialScan);
     }
     for (;;) {
@@ -754,7 +791,7 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
       o[t] = ok ? oj : 0;
       end[t] = ok ? oj + ((jc + 1 < F ? e1 : T) - e0) : 0;
     }
-    first_up<kResolveRV>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
+    first_up<kResolveRV, kFirst>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
 #pragma unroll
     for (int t = 0; t < kResolveRV; ++t) {
       if (v[t] < 0) continue;
@@ -775,8 +812,9 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
 constexpr int kPullBlock = 1024;
 // hot prefix staged by the pull: 144 KiB of bits plus 8 KiB of wave lists
 constexpr int kPullHotWords = 36864;
-// searches per thread
+// searches per thread, adjacencies each tests in its first step
 constexpr int kPullRV = 2;
+constexpr int kPullFirst = 4;
 
 __global__ __launch_bounds__(kPullBlock) void k_pull(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col,
@@ -787,7 +825,7 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
   __shared__ uint32_t s_prev[kPullHotWords];
   __shared__ int s_exw[WAVES][64];
   __shared__ uint32_t s_m[WAVES][64];
-  __shared__ unsigned long long s_red[2][WAVES];
+  __shared__ unsigned long long s_red[4][WAVES];
   if (!st->pull) return;
   const int k = st->k_fold;
   const uint8_t tprev = level_tag(k - 1);
@@ -807,7 +845,7 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
   const int64_t nw = (n_active + 31) >> 5;
   const int64_t nchunks = (nw + 63) >> 6;
   const int64_t nwaves = (int64_t)gridDim.x * WAVES;
-  unsigned long long my_cand = 0, my_edges = 0;
+  unsigned long long my_cand = 0, my_edges = 0, my_found = 0, my_fdeg = 0;
   for (int64_t c = (int64_t)blockIdx.x * WAVES + wid; c < nchunks; c += nwaves) {
     const int64_t w = (c << 6) + lane;
     uint32_t m = 0u;
@@ -845,7 +883,7 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
           end[t] = off[vv + 1];
         }
       }
-      first_up<kPullRV>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
+      first_up<kPullRV, kPullFirst>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
 #pragma unroll
       for (int t = 0; t < kPullRV; ++t) {
         if (v[t] < 0) continue;
@@ -855,6 +893,8 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
         const int32_t pc = inv ? inv[p[t]] : p[t];
         rpl[v[t]] = ((unsigned long long)k << 32) | (uint32_t)pc;
         mark[v[t]] = 1;
+        ++my_found;
+        my_fdeg += (unsigned long long)(end[t] - o[t]);
       }
     }
     // the wave's lists are rewritten by its next chunk
@@ -865,17 +905,27 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
   for (int d = 32; d >= 1; d >>= 1) {
     my_cand += __shfl_xor(my_cand, d, 64);
     my_edges += __shfl_xor(my_edges, d, 64);
+    my_found += __shfl_xor(my_found, d, 64);
+    my_fdeg += __shfl_xor(my_fdeg, d, 64);
   }
   if (lane == 0) {
     s_red[0][wid] = my_cand;
     s_red[1][wid] = my_edges;
+    s_red[2][wid] = my_found;
+    s_red[3][wid] = my_fdeg;
   }
   __syncthreads();
   if (tid == 0) {
-    unsigned long long a = 0, b = 0;
+    unsigned long long a = 0, b = 0, f = 0, fd = 0;
     for (int x = 0; x < WAVES; ++x) {
       a += s_red[0][x];
       b += s_red[1][x];
+      f += s_red[2][x];
+      fd += s_red[3][x];
+    }
+    if (f) {
+      atomicAdd(&st->pull_found, f);
+      atomicAdd(&st->pull_found_edges, fd);
     }
     if (b) atomicAdd(&st->pull_edges, b);
     if (k < kLevelHist && a) {

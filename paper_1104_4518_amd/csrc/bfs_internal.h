@@ -55,6 +55,11 @@ struct LevelState {
   int32_t pull_levels;   // levels computed by rows
   int32_t pad;
   unsigned long long pull_edges;   // adjacencies examined by the pull levels
+  // current pull level: vertices found and their adjacencies (the next
+  // level's input counter, known before finish)
+  unsigned long long pull_found, pull_found_edges;
+  int32_t qskip;   // the last finish built no queue (its successor pulls)
+  int32_t pad2;
   // input frontier counter of each level (profiling; levels < kLevelHist)
   unsigned long long hist[4096];
   int32_t hist_mark[4096];   // 0 claim, 1 mark-and-resolve, 2 pull

@@ -55,6 +55,21 @@ __device__ __forceinline__ bool mark_level(unsigned long long cin, int cbits,
          (long long)(cin & cmask) >= mp.min_vertices;
 }
 
+// Direction of a mark level's product with input counter cin: by rows (pull)
+// once pull_alpha times the frontier's adjacencies reach those of the
+// vertices still unvisited, which the searches read at most; seen = the
+// adjacencies of every visited vertex, the frontier's included. The level's
+// own expand decides, and the finish of a pull level decides ahead for the
+// next one from the same inputs.
+__device__ __forceinline__ bool pull_level(unsigned long long cin, int cbits,
+                                           unsigned long long seen, const MarkPolicy& mp) {
+  if (!mark_level(cin, cbits, mp) || mp.pull_alpha <= 0) return false;
+  const unsigned long long T = cin >> cbits;
+  const unsigned long long rest =
+      (unsigned long long)mp.nnz > seen ? (unsigned long long)mp.nnz - seen : 0ull;
+  return T * (unsigned long long)mp.pull_alpha >= rest;
+}
+
 
 // Mark expand (bfs_mark.hip): workgroups to launch (one per CU, its LDS holds
 // the hot prefix of the visited bitmap) and the launch itself; probe: 0 =

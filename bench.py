@@ -8,13 +8,13 @@ steps of per-root TEPS, with TEPS = (undirected edges of the searched
 component) / (BFS time), in GTEPS.
 
 The JSON line also carries:
-  roofline      the dominant level kernel on R-MAT, k_pull (the levels whose
-                product is computed by rows) or k_expand_mark (push levels),
-                whichever took longer: algorithmic bytes per launch / average
-                launch duration, both from HIP events recorded around every
-                launch of it on its stream (one launch per enqueued level;
-                launches on levels of the other kinds exit at once and count
-                too)
+  roofline      the mark-level kernel k_expand_mark (the dominant kernel on
+                R-MAT), which pushes a large frontier's adjacencies or, on a
+                pull level, computes the product by rows: algorithmic bytes
+                per launch / average launch duration, both from HIP events
+                recorded around every launch of it on its stream (one launch
+                per enqueued level; claim levels' launches exit at once and
+                count too)
   cpu_baseline  the CPU oracle (serial C) timed on a bounded sample of roots
   bfs_roofline_frac  whole-BFS algorithmic bytes / BFS time, per root
   spmspv        the 2D share (2^26 x 2^26 DCSC, 2^24 uniform nonzeros): 200
@@ -60,7 +60,7 @@ def mark_expand_bytes(levels) -> float:
 
 
 def pull_bytes(levels, n_active: int) -> float:
-    """Algorithmic bytes of the pull launches of one BFS, from its per-level
+    """Algorithmic bytes of the pull levels of one BFS, from its per-level
     record: per pull level the visited bits of the n_active vertices of
     positive degree; per searching vertex 8 B (its adjacency start); per
     examined adjacency 4 B + 1/8 B (the adjacency and the neighbour's
@@ -80,7 +80,7 @@ def bfs_bytes(n: int, edges: int, reached: int) -> float:
     return 4.125 * edges + 24.0 * reached + 8.0 * n + n / 4.0
 
 
-KERNEL_SOURCE = {"k_expand_mark": "bfs_mark.hip", "k_pull": "bfs_csr.hip"}
+KERNEL_SOURCES = {"k_expand_mark": ("bfs_mark.hip", "bfs_search.h")}
 
 
 def profiled_traffic(kernel: str, workload: str):
@@ -89,12 +89,14 @@ def profiled_traffic(kernel: str, workload: str):
     import hashlib
     import re
     prof = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
-    src = os.path.join(ROOT, "paper_1104_4518_amd", "csrc", KERNEL_SOURCE[kernel])
     try:
         text = open(prof).read()
         want = re.search(r"source_sha256_16:\s*([0-9a-f]+)", text).group(1)
         val = float(re.search(r"traffic_bytes_per_launch:\s*([0-9.]+)", text).group(1))
-        have = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES[kernel]:
+            h.update(open(os.path.join(ROOT, "paper_1104_4518_amd", "csrc", f), "rb").read())
+        have = h.hexdigest()[:16]
     except (OSError, AttributeError, ValueError):
         return None
     return val if have == want else None
@@ -184,9 +186,8 @@ def bfs_leg(args, torch, graphgen, B):
     # the pull scans the vertices of positive degree of the degree-ordered copy
     # (graphs of 2^20 vertices and more), else all vertices
     n_active = int((deg > 0).sum()) if g.n >= (1 << 20) else g.n
-    kb = {"k_expand_mark": 0.0, "k_pull": 0.0}
-    kms = {"k_expand_mark": 0.0, "k_pull": 0.0}
-    launches = 0
+    exp_bytes = exp_ms = 0.0
+    exp_launches = 0
     for i, st in enumerate(stats):
         ms = starts[i].elapsed_time(ends[i])
         if st.reached == giant_size:
@@ -194,18 +195,15 @@ def bfs_leg(args, torch, graphgen, B):
             per_root_gteps.append(m_r / (ms * 1e-3) / 1e9)
             per_root_frac.append(bfs_bytes(g.n, st.edges_traversed, st.reached) /
                                  (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
-        kb["k_expand_mark"] += mark_expand_bytes(levels[i])
-        kb["k_pull"] += pull_bytes(levels[i], n_active)
-        kms["k_expand_mark"] += st.mark_ms
-        kms["k_pull"] += st.pull_ms
-        launches += st.expand_launches   # one launch of each per enqueued level
+        # the mark-level kernel: push levels' and pull levels' work
+        exp_bytes += mark_expand_bytes(levels[i]) + pull_bytes(levels[i], n_active)
+        exp_ms += st.mark_ms + st.pull_ms
+        exp_launches += st.expand_launches   # one launch per enqueued level
     value = harmonic(per_root_gteps)
-    kern = max(kms, key=lambda k: kms[k])
-    exp_bytes, exp_ms, exp_launches = kb[kern], kms[kern], launches
+    kern = "k_expand_mark"
     achieved = exp_bytes / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else 0.0
     log(f"timed {args.steps} roots in {wall:.3f}s wall; {value:.2f} GTEPS; {kern} "
-        f"{exp_launches} launches avg {exp_ms / max(exp_launches, 1) * 1e3:.1f} us; "
-        f"k_expand_mark {kms['k_expand_mark']:.3f} ms, k_pull {kms['k_pull']:.3f} ms in total")
+        f"{exp_launches} launches avg {exp_ms / max(exp_launches, 1) * 1e3:.1f} us")
     res = {
         "value": value,
         "wall": wall,

@@ -48,6 +48,7 @@
 // yields the degree prefix the next level needs to split its work by edges.
 #include "bfs_internal.h"
 #include "bfs_level.h"
+#include "bfs_search.h"
 
 #include <algorithm>
 #include <cstddef>
@@ -145,21 +146,6 @@ __device__ __forceinline__ void block_scan2(long long c, long long d, long long*
   ex_d = bd + id - d;
 }
 
-// Position of the r-th (0-based) set bit of x; x has more than r set bits.
-__device__ __forceinline__ int select_bit(uint32_t x, int r) {
-  int pos = 0;
-  int c = __popc(x & 0xFFFFu);
-  if (r >= c) { r -= c; x >>= 16; pos += 16; }
-  c = __popc(x & 0xFFu);
-  if (r >= c) { r -= c; x >>= 8; pos += 8; }
-  c = __popc(x & 0xFu);
-  if (r >= c) { r -= c; x >>= 4; pos += 4; }
-  c = __popc(x & 0x3u);
-  if (r >= c) { r -= c; x >>= 2; pos += 2; }
-  if (r >= (int)(x & 1u)) pos += 1;
-  return pos;
-}
-
 // Map the edge tiles of the next level that start inside [e, e + d) to
 // queue entry j.
 __device__ __forceinline__ void map_tiles(int32_t* __restrict__ jstart, long long e, long long d,
@@ -167,15 +153,41 @@ __device__ __forceinline__ void map_tiles(int32_t* __restrict__ jstart, long lon
   for (long long w = (e + kTileJ - 1) / kTileJ; w * kTileJ < e + d; ++w) jstart[w] = j;
 }
 
+// Bitmap of the hot prefix's vertices at level k-1 (mark byte = its tag),
+// built by the claim expand's threads at the start of every mark level for
+// the workgroups of k_resolve and k_pull to copy into LDS. No launch of
+// level k changes a tag of level k-1 (they only turn 0 into 1 and 1 into
+// the tag of level k).
+__device__ __forceinline__ void build_prev_bits(const uint8_t* __restrict__ mark, int k, int hw,
+                                                uint32_t* __restrict__ prev_bits) {
+  const uint4* __restrict__ mark4 = reinterpret_cast<const uint4*>(mark);
+  const uint32_t tp4 = 0x01010101u * level_tag(k - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < hw; i += stride) {
+    const uint4 a = mark4[2 * i], b = mark4[2 * i + 1];
+    const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t bits = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const uint32_t e = x[t] ^ tp4;   // zero bytes = tag of level k-1
+#pragma unroll
+      for (int byte = 0; byte < 4; ++byte)
+        if (((e >> (8 * byte)) & 0xFFu) == 0u) bits |= 1u << (4 * t + byte);
+    }
+    prev_bits[i] = bits;
+  }
+}
+
 // expand(k), claim levels; on a mark level it only does the level's
-// bookkeeping and leaves the edges to k_expand_mark.
+// bookkeeping and builds the hot bitmap of level k-1, leaving the edges to
+// k_expand_mark or k_pull.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_expand(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const uint32_t* __restrict__ vis, unsigned long long* __restrict__ rpl,
     uint8_t* __restrict__ mark, Queues q, int32_t* __restrict__ jstart_base, int64_t njs,
     int32_t* __restrict__ zq, LevelState* st, int cbits, MarkPolicy mp,
-    const int32_t* __restrict__ inv) {
+    const int32_t* __restrict__ inv, int hw, uint32_t* __restrict__ prev_bits) {
   constexpr int WAVES = BLOCK / 64;
   __shared__ __align__(16) long long s_qe[kTileJ + 1];
   __shared__ int32_t s_ov[kTileJ], s_od[kTileJ];
@@ -214,7 +226,11 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
       st->hist_pe[k] = 0ull;
     }
   }
-  if (F == 0 || mark_level(cin, cbits, mp)) return;
+  if (F == 0) return;
+  if (mark_level(cin, cbits, mp)) {
+    build_prev_bits(mark, k, hw, prev_bits);
+    return;
+  }
   const int64_t njt = (T + kTileJ - 1) / kTileJ;   // jstart tiles of this level
   // tile map of frontier k-1 (read) and of frontier k (written here)
   const int32_t* __restrict__ jstart = jstart_base + (int64_t)(kin & 1) * njs;
@@ -572,182 +588,28 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
 // resolve(k), mark levels: the parent of each vertex of the new frontier is
 // its first neighbour one level up (tag of level k-1) in ascending adjacency
 // order, i.e. the minimum-id frontier vertex adjacent to it. Each thread takes
-// RV vertices at once and tests their first kFirst adjacencies together, then
-// scans on four at a time up to kSerialScan; the wave finishes the longer
-// searches together, 64 adjacencies per step. For a large frontier the
-// workgroup first turns the tags of the hot prefix into an LDS bitmap of
-// level k-1, so most tests (hub neighbours) stay in LDS.
+// RV vertices at once and tests their first adjacencies together from the
+// head copy, then scans their rows on, four at a time up to kSerialScan; the
+// wave finishes the longer searches together, 64 adjacencies per step. For a
+// large frontier the workgroup first turns the tags of the hot prefix into an
+// LDS bitmap of level k-1, so most tests (hub neighbours) stay in LDS.
 constexpr int kResolveBlock = 1024;
 constexpr int kResolveRV = 4;
-constexpr int kFirst = 8;
 
-// Bitmap of the hot prefix's vertices at level k-1 (mark byte = its tag),
-// built once per mark level, ahead of its expand, for the workgroups of
-// k_resolve and k_pull to copy into LDS. No launch of level k changes a tag
-// of level k-1 (they only turn 0 into 1 and 1 into the tag of level k).
-__global__ void k_prev_bits(const uint8_t* __restrict__ mark, const LevelState* __restrict__ st,
-                            int cbits, MarkPolicy mp, int hw, uint32_t* __restrict__ prev_bits) {
-  const int k = st->k_fold;
-  const unsigned long long cmask = (1ull << cbits) - 1;
-  const unsigned long long cin = st->ctr[(k - 1) % 3];
-  if ((cin & cmask) == 0 || !mark_level(cin, cbits, mp)) return;
-  const uint4* __restrict__ mark4 = reinterpret_cast<const uint4*>(mark);
-  const uint32_t tp4 = 0x01010101u * level_tag(k - 1);
+__global__ void k_build_head(int64_t n, const int64_t* __restrict__ off,
+                             const int32_t* __restrict__ col, int4* __restrict__ head) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < hw; i += stride) {
-    const uint4 a = mark4[2 * i], b = mark4[2 * i + 1];
-    const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-    uint32_t bits = 0;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const uint32_t e = x[t] ^ tp4;   // zero bytes = tag of level k-1
-#pragma unroll
-      for (int byte = 0; byte < 4; ++byte)
-        if (((e >> (8 * byte)) & 0xFFu) == 0u) bits |= 1u << (4 * t + byte);
-    }
-    prev_bits[i] = bits;
-  }
-}
-
-__device__ __forceinline__ bool prev_level(int32_t u, int64_t hotv, const uint32_t* s_prev,
-                                           const uint8_t* __restrict__ mark, uint8_t tprev) {
-  return u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u : mark[u] == tprev;
-}
-
-// First neighbour one level up (mark tag tprev, or a bit of the LDS bitmap
-// s_prev below hotv) in each of the thread's RV adjacency ranges
-// [o[t], end[t]): p[t] = that neighbour and at[t] = its position, or p[t] =
-// -1 and at[t] = end[t]. Entries with v[t] < 0 have empty ranges. The RV
-// searches of a thread test their first KF adjacencies together, then
-// advance four at a time up to kSerialScan; the wave finishes the longer
-// searches together, 64 adjacencies per step, so every lane of the wave
-// must make the call.
-template <int RV, int KF>
-__device__ __forceinline__ void first_up(const int32_t* __restrict__ col,
-                                         const uint8_t* __restrict__ mark,
-                                         const uint32_t* s_prev, int64_t hotv, uint8_t tprev,
-                                         int lane, const int32_t (&v)[RV], const int64_t (&o)[RV],
-                                         const int64_t (&end)[RV], int32_t (&p)[RV],
-                                         int64_t (&at)[RV]) {
-  // first KF adjacencies of all RV vertices together; the LDS tests of
-  // hot neighbours come first, so mark bytes are read only for the cold
-  // neighbours ahead of the first hot hit
-  int32_t u[RV][KF];
-#pragma unroll
-  for (int t = 0; t < RV; ++t)
-#pragma unroll
-    for (int i = 0; i < KF; ++i) u[t][i] = o[t] + i < end[t] ? col[o[t] + i] : -1;
-  int hh[RV];
-#pragma unroll
-  for (int t = 0; t < RV; ++t) {
-    hh[t] = KF;
-#pragma unroll
-    for (int i = KF - 1; i >= 0; --i)
-      if (u[t][i] >= 0 && u[t][i] < hotv && ((s_prev[u[t][i] >> 5] >> (u[t][i] & 31)) & 1u))
-        hh[t] = i;
-  }
-  uint8_t cm[RV][KF];
-#pragma unroll
-  for (int t = 0; t < RV; ++t)
-#pragma unroll
-    for (int i = 0; i < KF; ++i)
-      cm[t][i] = (i < hh[t] && u[t][i] >= hotv) ? mark[u[t][i]] : (uint8_t)0;
-#pragma unroll
-  for (int t = 0; t < RV; ++t) {
-    p[t] = hh[t] < KF ? u[t][hh[t] < KF ? hh[t] : 0] : -1;
-    at[t] = hh[t] < KF ? o[t] + hh[t] : end[t];
-#pragma unroll
-    for (int i = KF - 1; i >= 0; --i)
-      if (i < hh[t] && cm[t][i] == tprev) {
-        p[t] = u[t][i];
-        at[t] = o[t] + i;
-      }
-  }
-  // continuation up to kSerialScan adjacencies, four per step, the RV
-  // searches of the thread advancing together (their loads overlap)
-  bool pending[RV];
-  {
-    int64_t e[RV], lim[RV];
-#pragma unroll
-    for (int t = 0; t < RV; ++t) {
-      e[t] = o[t] + KF;
-      lim[t] = min(end[t], o[t] + (int64_t)kSerialScan);
-    }
-    for (;;) {
-      bool any = false;
-      int32_t w4[RV][4];
-#pragma unroll
-      for (int t = 0; t < RV; ++t) {
-        const bool act = p[t] < 0 && e[t] < lim[t];
-        any |= act;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) w4[t][i] = (act && e[t] + i < lim[t]) ? col[e[t] + i] : -1;
-      }
-      if (!any) break;
-      uint8_t m4[RV][4];
-#pragma unroll
-      for (int t = 0; t < RV; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          m4[t][i] = (w4[t][i] >= hotv) ? mark[w4[t][i]] : (uint8_t)0;
-#pragma unroll
-      for (int t = 0; t < RV; ++t) {
-#pragma unroll
-        for (int i = 3; i >= 0; --i) {
-          const int32_t u = w4[t][i];
-          if (u < 0) continue;
-          const bool hit = u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u
-                                    : m4[t][i] == tprev;
-          if (hit) {
-            p[t] = u;
-            at[t] = e[t] + i;
-          }
-        }
-        e[t] += 4;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < RV; ++t)
-      pending[t] = v[t] >= 0 && p[t] < 0 && end[t] - o[t] > kSerialScan;
-  }
-  // the wave scans the rest of each long adjacency list together
-#pragma unroll
-  for (int t = 0; t < RV; ++t) {
-    for (;;) {
-      const unsigned long long pend = wave_ballot(pending[t]);
-      if (!pend) break;
-      const int leader = __ffsll((long long)pend) - 1;
-      const int64_t lo = shfl_ll(o[t] + kSerialScan, leader);
-      const int64_t hi = shfl_ll(end[t], leader);
-      int32_t found = -1;
-      int64_t fat = hi;
-      for (int64_t e0 = lo; e0 < hi; e0 += 64) {
-        const int64_t e = e0 + lane;
-        int32_t uu = 0;
-        bool hit = false;
-        if (e < hi) {
-          uu = col[e];
-          hit = prev_level(uu, hotv, s_prev, mark, tprev);
-        }
-        const unsigned long long hb = wave_ballot(hit);
-        if (hb) {
-          const int src = __ffsll((long long)hb) - 1;
-          found = __shfl(uu, src, 64);
-          fat = e0 + src;
-          break;
-        }
-      }
-      if (lane == leader) {
-        p[t] = found;
-        at[t] = fat;
-        pending[t] = false;
-      }
-    }
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int64_t o = off[v];
+    const int64_t d = off[v + 1] - o;
+    head[v] = make_int4(d > 0 ? col[o] : -1, d > 1 ? col[o + 1] : -1, d > 2 ? col[o + 2] : -1,
+                        (int)d);
   }
 }
 
 __global__ __launch_bounds__(kResolveBlock) void k_resolve(
-    const int32_t* __restrict__ col, unsigned long long* __restrict__ rpl,
+    const int32_t* __restrict__ col, const int4* __restrict__ head,
+    unsigned long long* __restrict__ rpl,
     const uint8_t* __restrict__ mark, Queues q, const LevelState* __restrict__ st, int cbits,
     MarkPolicy mp, const int32_t* __restrict__ inv, int hw,
     const uint32_t* __restrict__ prev_bits) {
@@ -765,7 +627,7 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
   const uint8_t tprev = level_tag(k - 1);
   const int tid = threadIdx.x;
   const int lane = lane_id();
-  // stage the hot prefix (built once by k_prev_bits) only when the
+  // stage the hot prefix (built by the claim expand) only when the
   // frontier is large enough to repay it
   const int64_t hotv = F >= ((int64_t)hw << 5) ? ((int64_t)hw << 5) : 0;
   if (hotv) {
@@ -791,146 +653,15 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
       o[t] = ok ? oj : 0;
       end[t] = ok ? oj + ((jc + 1 < F ? e1 : T) - e0) : 0;
     }
-    first_up<kResolveRV, kFirst>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
+    int pos[kResolveRV];
+    int32_t deg[kResolveRV];
+    head_step<kResolveRV>(head, mark, s_prev, hotv, tprev, v, p, pos, deg);
+    first_up_rest<kResolveRV>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
 #pragma unroll
     for (int t = 0; t < kResolveRV; ++t) {
       if (v[t] < 0) continue;
       const int32_t pc = (inv && p[t] >= 0) ? inv[p[t]] : p[t];
       rpl[v[t]] = ((unsigned long long)k << 32) | (uint32_t)pc;
-    }
-  }
-}
-
-// pull(k), the product of a level computed by rows: every unvisited vertex
-// of positive degree searches its ascending adjacency list for the first
-// vertex one level up (first_up), which is its parent; the masked product
-// of section 3.2 restricted to the rows the mask leaves, the same entries
-// as the push. A vertex that finds one gets its parent and level and is
-// marked touched (byte 1) for finish(k). Each wave takes 64 words of the
-// visited bitmap (2048 vertices), lists their unvisited vertices in LDS and
-// hands them to its lanes RV at a time, so the searches fill the wave.
-constexpr int kPullBlock = 1024;
-// hot prefix staged by the pull: 144 KiB of bits plus 8 KiB of wave lists
-constexpr int kPullHotWords = 36864;
-// searches per thread, adjacencies each tests in its first step
-constexpr int kPullRV = 2;
-constexpr int kPullFirst = 4;
-
-__global__ __launch_bounds__(kPullBlock) void k_pull(
-    const int64_t* __restrict__ off, const int32_t* __restrict__ col,
-    const uint32_t* __restrict__ vis, unsigned long long* __restrict__ rpl,
-    uint8_t* __restrict__ mark, LevelState* st, MarkPolicy mp, const int32_t* __restrict__ inv,
-    int hw, const uint32_t* __restrict__ prev_bits, int64_t n_active) {
-  constexpr int WAVES = kPullBlock / 64;
-  __shared__ uint32_t s_prev[kPullHotWords];
-  __shared__ int s_exw[WAVES][64];
-  __shared__ uint32_t s_m[WAVES][64];
-  __shared__ unsigned long long s_red[4][WAVES];
-  if (!st->pull) return;
-  const int k = st->k_fold;
-  const uint8_t tprev = level_tag(k - 1);
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wid = tid >> 6;
-  // the hot prefix goes to LDS when the unvisited vertices' adjacencies
-  // (what the searches read at most) number at least 4 per staged vertex
-  const int hwp = min(hw, kPullHotWords);
-  const unsigned long long seen = st->edges;
-  const unsigned long long rest =
-      (unsigned long long)mp.nnz > seen ? (unsigned long long)mp.nnz - seen : 0ull;
-  const int64_t hotv = rest >= ((unsigned long long)hwp << 7) ? ((int64_t)hwp << 5) : 0;
-  if (hotv)
-    for (int i = tid; i < hwp; i += kPullBlock) s_prev[i] = prev_bits[i];
-  __syncthreads();
-  const int64_t nw = (n_active + 31) >> 5;
-  const int64_t nchunks = (nw + 63) >> 6;
-  const int64_t nwaves = (int64_t)gridDim.x * WAVES;
-  unsigned long long my_cand = 0, my_edges = 0, my_found = 0, my_fdeg = 0;
-  for (int64_t c = (int64_t)blockIdx.x * WAVES + wid; c < nchunks; c += nwaves) {
-    const int64_t w = (c << 6) + lane;
-    uint32_t m = 0u;
-    if (w < nw) {
-      m = ~vis[w];
-      const int64_t left = n_active - (w << 5);   // >= 1 for w < nw
-      if (left < 32) m &= (1u << left) - 1u;
-    }
-    const int cnt = __popc(m);
-    const int incl = (int)wave_incl_scan((long long)cnt);
-    const int total = __shfl(incl, 63, 64);
-    s_exw[wid][lane] = incl - cnt;
-    s_m[wid][lane] = m;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int r = 0; r < total; r += 64 * kPullRV) {
-      int32_t v[kPullRV], p[kPullRV];
-      int64_t o[kPullRV], end[kPullRV], at[kPullRV];
-#pragma unroll
-      for (int t = 0; t < kPullRV; ++t) {
-        const int i = r + t * 64 + lane;
-        v[t] = -1;
-        o[t] = 0;
-        end[t] = 0;
-        if (i < total) {
-          int lo = 0;   // last lane whose list starts at or before i
-#pragma unroll
-          for (int step = 32; step; step >>= 1)
-            if (lo + step <= 63 && s_exw[wid][lo + step] <= i) lo += step;
-          const int32_t vv =
-              (int32_t)((((c << 6) + lo) << 5) + select_bit(s_m[wid][lo], i - s_exw[wid][lo]));
-          v[t] = vv;
-          o[t] = off[vv];
-          end[t] = off[vv + 1];
-        }
-      }
-      first_up<kPullRV, kPullFirst>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
-#pragma unroll
-      for (int t = 0; t < kPullRV; ++t) {
-        if (v[t] < 0) continue;
-        my_cand += end[t] > o[t];   // vertices of degree 0 have nothing to search
-        my_edges += (unsigned long long)((p[t] >= 0 ? at[t] + 1 : end[t]) - o[t]);
-        if (p[t] < 0) continue;
-        const int32_t pc = inv ? inv[p[t]] : p[t];
-        rpl[v[t]] = ((unsigned long long)k << 32) | (uint32_t)pc;
-        mark[v[t]] = 1;
-        ++my_found;
-        my_fdeg += (unsigned long long)(end[t] - o[t]);
-      }
-    }
-    // the wave's lists are rewritten by its next chunk
-    __builtin_amdgcn_wave_barrier();
-  }
-  // statistics: candidates and examined adjacencies of the level
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    my_cand += __shfl_xor(my_cand, d, 64);
-    my_edges += __shfl_xor(my_edges, d, 64);
-    my_found += __shfl_xor(my_found, d, 64);
-    my_fdeg += __shfl_xor(my_fdeg, d, 64);
-  }
-  if (lane == 0) {
-    s_red[0][wid] = my_cand;
-    s_red[1][wid] = my_edges;
-    s_red[2][wid] = my_found;
-    s_red[3][wid] = my_fdeg;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    unsigned long long a = 0, b = 0, f = 0, fd = 0;
-    for (int x = 0; x < WAVES; ++x) {
-      a += s_red[0][x];
-      b += s_red[1][x];
-      f += s_red[2][x];
-      fd += s_red[3][x];
-    }
-    if (f) {
-      atomicAdd(&st->pull_found, f);
-      atomicAdd(&st->pull_found_edges, fd);
-    }
-    if (b) atomicAdd(&st->pull_edges, b);
-    if (k < kLevelHist && a) {
-      atomicAdd(&st->hist_pc[k], a);
-      atomicAdd(&st->hist_pe[k], b);
     }
   }
 }
@@ -1074,6 +805,14 @@ int csr_alloc_workspace(bfs_graph* g) {
     c.hot_slices = mark_expand_grid(g->device);
     BFS_HIP(hipMalloc(&c.hot_new, (size_t)c.hot_slices * c.hot_words * 4));
     BFS_HIP(hipMalloc(&c.prev_bits, (size_t)c.hot_words * 4));
+    // head copy of the rows the searches read (the level kernels' CSR)
+    if (!c.relabeled) c.n_active = c.n;
+    BFS_HIP(hipMalloc(&c.head, (size_t)std::max<int64_t>(c.n_active, 1) * 16));
+    k_build_head<<<4096, 256>>>(c.n_active, c.relabeled ? c.roff : c.off,
+                                c.relabeled ? c.rcol : c.col, c.head);
+    BFS_HIP(hipGetLastError());
+    BFS_HIP(hipDeviceSynchronize());
+    g->device_bytes += std::max<int64_t>(c.n_active, 1) * 16;
     g->device_bytes += (int64_t)c.hot_words * 4;
     g->device_bytes += (int64_t)c.hot_slices * c.hot_words * 4;
   }
@@ -1088,6 +827,7 @@ void csr_free(bfs_graph* g) {
   (void)hipFree(c.col);
   (void)hipFree(c.vis);
   (void)hipFree(c.rpl);
+  (void)hipFree(c.head);
   for (int b = 0; b < 2; ++b) {
     (void)hipFree(c.qv[b]);
     (void)hipFree(c.qo[b]);
@@ -1263,12 +1003,10 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   // workgroups; the mark expand runs one 1024-thread workgroup per CU (its
   // LDS holds the hot prefix of the visited bitmap)
 
-  static int ge_cache = 0, gf_cache = 0, gr_cache = 0, gp_cache = 0;
+  static int ge_cache = 0, gf_cache = 0, gr_cache = 0;
   if (!ge_cache) ge_cache = grid_for(g->device, (const void*)k_expand<kExpandBlock>, kExpandBlock, 8);
   if (!gf_cache) gf_cache = grid_for(g->device, (const void*)k_finish<kFinishBlock>, kFinishBlock, 4);
   if (!gr_cache) gr_cache = grid_for(g->device, (const void*)k_resolve, kResolveBlock, 1);
-  if (!gp_cache) gp_cache = grid_for(g->device, (const void*)k_pull, kPullBlock, 1);
-  const int gp = gp_cache;
   const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache;
   const int gm = g->opt.grid_blocks > 0 ? std::min(g->opt.grid_blocks, c.hot_slices) : c.hot_slices;
   const int gf = gf_cache;
@@ -1280,34 +1018,47 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   const bool prof = g->opt.profile > 0;
   const int probe = g->opt.cold_probe == 3 ? 0 : g->opt.cold_probe;
   // One level: its launches; ev_base >= 0 brackets them with events
-  // ev_base .. ev_base + 4 (claim expand + hot bits | mark expand | pull |
+  // ev_base .. ev_base + 3 (claim expand or hot bits | mark expand or pull |
   // finish + resolve).
   auto enqueue_level = [&](hipStream_t st, int64_t ev_base) -> int {
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base], st));
     k_expand<kExpandBlock><<<ge, kExpandBlock, 0, st>>>(koff, kcol, c.vis, c.rpl,
                                                         c.mark, q, c.jstart, c.njstart, c.zq,
-                                                        c.state, c.cbits, mp, kinv);
-    if (mp.symmetric)
-      k_prev_bits<<<(c.hot_words + 255) / 256, 256, 0, st>>>(c.mark, c.state, c.cbits, mp,
-                                                             c.hot_words, c.prev_bits);
+                                                        c.state, c.cbits, mp, kinv,
+                                                        c.hot_words, c.prev_bits);
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 1], st));
     if (mp.symmetric) {
-      mark_expand_launch(gm, st, kcol, c.vis, c.mark, q, c.jstart, c.njstart, c.state, c.cbits,
-                         mp, c.hot_words, c.hot_new, c.n, probe);
+      MarkArgs a;
+      a.col = kcol;
+      a.off = koff;
+      a.head = c.head;
+      a.vis = c.vis;
+      a.mark = c.mark;
+      a.rpl = c.rpl;
+      a.inv = kinv;
+      a.q = q;
+      a.jstart = c.jstart;
+      a.njs = c.njstart;
+      a.st = c.state;
+      a.cbits = c.cbits;
+      a.mp = mp;
+      a.hw = c.hot_words;
+      a.hot_new = c.hot_new;
+      a.prev_bits = c.prev_bits;
+      a.n = c.n;
+      a.n_active = n_active;
+      a.probe = probe;
+      mark_expand_launch(gm, st, a);
     }
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 2], st));
-    if (mp.symmetric && mp.pull_alpha > 0)
-      k_pull<<<gp, kPullBlock, 0, st>>>(koff, kcol, c.vis, c.rpl, c.mark, c.state,
-                                        mp, kinv, c.hot_words, c.prev_bits, n_active);
-    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
     k_finish<kFinishBlock><<<gf, kFinishBlock, 0, st>>>(koff, c.vis, c.mark, q, c.jstart,
                                                         c.njstart, c.zq, c.state, c.cbits, c.n,
                                                         c.nwords, mp, c.hot_words, c.hot_new,
                                                         gm);
     if (mp.symmetric)
-      k_resolve<<<gr, kResolveBlock, 0, st>>>(kcol, c.rpl, c.mark, q, c.state,
+      k_resolve<<<gr, kResolveBlock, 0, st>>>(kcol, c.head, c.rpl, c.mark, q, c.state,
                                               c.cbits, mp, kinv, c.hot_words, c.prev_bits);
-    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 4], st));
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
     return BFS_OK;
   };
   int64_t k = 0;
@@ -1367,14 +1118,14 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     for (;;) {
       for (int b = 0; b < batch; ++b) {
         if (prof) {
-          const size_t need = 5 * (size_t)(k + 1) + 2;
+          const size_t need = 4 * (size_t)(k + 1) + 2;
           while (g->ev.size() < need) {
             hipEvent_t ev;
             BFS_HIP(hipEventCreate(&ev));
             g->ev.push_back(ev);
           }
         }
-        const int rc = enqueue_level(s, prof ? 2 + 5 * k : -1);
+        const int rc = enqueue_level(s, prof ? 2 + 4 * k : -1);
         if (rc != BFS_OK) return rc;
         ++k;
       }
@@ -1416,15 +1167,21 @@ int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st) {
   st->pull_levels = h.pull_levels;
   st->pull_edges = (int64_t)h.pull_edges;
   if (g->profiled == 1) {
+    // the mark kernel's time goes to mark_ms on push levels, pull_ms on
+    // pull levels (index k + 1 of the history is launch k)
+    const int nl = std::min(g->expand_launches, kLevelHist - 1);
+    std::vector<int32_t> kind((size_t)nl + 1, 0);
+    if (nl > 0)
+      BFS_HIP(hipMemcpy(kind.data(), g->csr.state->hist_mark, kind.size() * 4,
+                        hipMemcpyDeviceToHost));
     double sum = 0.0, msum = 0.0, psum = 0.0;
     for (int k = 0; k < g->expand_launches; ++k) {
-      float ms = 0.f, mm = 0.f, pm = 0.f;
-      BFS_HIP(hipEventElapsedTime(&ms, g->ev[2 + 5 * k], g->ev[5 + 5 * k]));
-      BFS_HIP(hipEventElapsedTime(&mm, g->ev[3 + 5 * k], g->ev[4 + 5 * k]));
-      BFS_HIP(hipEventElapsedTime(&pm, g->ev[4 + 5 * k], g->ev[5 + 5 * k]));
+      float ms = 0.f, mm = 0.f;
+      BFS_HIP(hipEventElapsedTime(&ms, g->ev[2 + 4 * k], g->ev[4 + 4 * k]));
+      BFS_HIP(hipEventElapsedTime(&mm, g->ev[3 + 4 * k], g->ev[4 + 4 * k]));
       sum += ms;
-      msum += mm;
-      psum += pm;
+      if (k < nl && kind[(size_t)k + 1] == 2) psum += mm;
+      else msum += mm;
     }
     st->mark_ms = msum;
     st->pull_ms = psum;
@@ -1459,16 +1216,15 @@ int csr_level_info(bfs_graph* g, bfs_level_info_t* out, int32_t capacity, int32_
     L.edges = (int64_t)(hist[(size_t)k] >> g->csr.cbits);
     L.pull_candidates = (int64_t)hpc[(size_t)k];
     L.pull_edges = (int64_t)hpe[(size_t)k];
-    float a = 0.f, m = 0.f, pl = 0.f, b = 0.f;
+    float a = 0.f, m = 0.f, b = 0.f;
     if (g->profiled == 1) {   // per-level events exist (not in graph mode)
-      BFS_HIP(hipEventElapsedTime(&a, g->ev[2 + 5 * i], g->ev[5 + 5 * i]));
-      BFS_HIP(hipEventElapsedTime(&m, g->ev[3 + 5 * i], g->ev[4 + 5 * i]));
-      BFS_HIP(hipEventElapsedTime(&pl, g->ev[4 + 5 * i], g->ev[5 + 5 * i]));
-      BFS_HIP(hipEventElapsedTime(&b, g->ev[5 + 5 * i], g->ev[6 + 5 * i]));
+      BFS_HIP(hipEventElapsedTime(&a, g->ev[2 + 4 * i], g->ev[4 + 4 * i]));
+      BFS_HIP(hipEventElapsedTime(&m, g->ev[3 + 4 * i], g->ev[4 + 4 * i]));
+      BFS_HIP(hipEventElapsedTime(&b, g->ev[4 + 4 * i], g->ev[5 + 4 * i]));
     }
     L.expand_ms = a;
-    L.mark_ms = m;
-    L.pull_ms = pl;
+    L.mark_ms = L.mark == 2 ? 0.0 : m;
+    L.pull_ms = L.mark == 2 ? m : 0.0;
     L.finish_ms = b;
   }
   *count = g->expand_launches;

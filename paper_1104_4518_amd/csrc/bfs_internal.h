@@ -85,6 +85,7 @@ struct CsrDev {
   // workspace
   uint32_t* vis = nullptr;       // visited bitmap, ceil(n / 32) words
   unsigned long long* rpl = nullptr;   // n: (level << 32) | parent per level-kernel id
+  int4* head = nullptr;          // symmetric: first 3 adjacencies and degree per vertex
   int64_t nwords = 0;
   int32_t* qv[2] = {nullptr, nullptr};   // frontier vertex ids
   int64_t* qo[2] = {nullptr, nullptr};   // row start off[v] of each entry

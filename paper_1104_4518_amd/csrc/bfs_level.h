@@ -71,13 +71,31 @@ __device__ __forceinline__ bool pull_level(unsigned long long cin, int cbits,
 }
 
 
-// Mark expand (bfs_mark.hip): workgroups to launch (one per CU, its LDS holds
-// the hot prefix of the visited bitmap) and the launch itself; probe: 0 =
-// by reached fraction, 1 = mark byte, 2 = visited word first.
+// The mark-level kernel (bfs_mark.hip): on a push level the mark expand, on
+// a pull level the pull; one 1024-thread workgroup per CU (its LDS holds
+// the hot prefix of a bitmap). probe: 0 = by reached fraction, 1 = mark
+// byte, 2 = visited word first (push levels).
+struct MarkArgs {
+  const int32_t* col;
+  const int64_t* off;
+  const int4* head;
+  const uint32_t* vis;
+  uint8_t* mark;
+  unsigned long long* rpl;
+  const int32_t* inv;
+  Queues q;
+  const int32_t* jstart;
+  int64_t njs;
+  LevelState* st;
+  int cbits;
+  MarkPolicy mp;
+  int hw;
+  uint32_t* hot_new;
+  const uint32_t* prev_bits;
+  int64_t n, n_active;
+  int probe;
+};
 int mark_expand_grid(int device);
-void mark_expand_launch(int grid, hipStream_t s, const int32_t* col, const uint32_t* vis,
-                        uint8_t* mark, const Queues& q, const int32_t* jstart_base, int64_t njs,
-                        const LevelState* st, int cbits, const MarkPolicy& mp, int hw,
-                        uint32_t* hot_new, int64_t n, int probe);
+void mark_expand_launch(int grid, hipStream_t s, const MarkArgs& a);
 
 }  // namespace bfsi

@@ -2,8 +2,10 @@
 // level-synchronous BFS, section 3.2's masked (select, min) product): every
 // adjacency of the frontier is streamed once and its target recorded as
 // touched, without atomics per edge. finish(k) and resolve(k) in bfs_csr.hip
-// turn the touched set into the next frontier and give it parents.
+// turn the touched set into the next frontier and give it parents. The same
+// launch runs a pull level's product by rows (pull_body) instead.
 #include "bfs_level.h"
+#include "bfs_search.h"
 
 #include <algorithm>
 
@@ -145,15 +147,35 @@ __device__ __forceinline__ void tile_targets(const int32_t* __restrict__ col,
 // and the mark byte only for an unvisited target: the bitmap is eight times
 // denser than the bytes and stays in L2, which pays once most targets are
 // visited. probe = 1 always reads the byte.
-__global__ __launch_bounds__(kMarkBlock) void k_expand_mark(
-    const int32_t* __restrict__ col, const uint32_t* __restrict__ vis,
-    uint8_t* __restrict__ mark, Queues q, const int32_t* __restrict__ jstart_base, int64_t njs,
-    const LevelState* __restrict__ st, int cbits, MarkPolicy mp, int hw,
-    uint32_t* __restrict__ hot_new, int64_t n, int probe) {
+constexpr int kPushLdsBytes = kHotWordsMax * 4 + (kMarkBlock / 64) * (kTileJ / 32) * 4;
+constexpr int kMarkLdsBytes = kPushLdsBytes > kPullLdsBytes ? kPushLdsBytes : kPullLdsBytes;
+static_assert(kPullBlock == kMarkBlock, "the pull runs in the mark expand's workgroups");
+
+__global__ __launch_bounds__(kMarkBlock) void k_expand_mark(MarkArgs a) {
   constexpr int WAVES = kMarkBlock / 64;
   constexpr int STEPS = kTileJ / 64;   // edges per lane per tile
-  __shared__ uint32_t s_hot[kHotWordsMax];
-  __shared__ uint32_t s_starts[WAVES][kTileJ / 32];
+  __shared__ __align__(16) uint8_t s_lds[kMarkLdsBytes];
+  if (a.st->pull) {
+    pull_body(a.off, a.col, a.head, a.vis, a.rpl, a.mark, a.st, a.mp, a.inv, a.hw, a.prev_bits,
+              a.n_active, s_lds);
+    return;
+  }
+  const int32_t* __restrict__ col = a.col;
+  const uint32_t* __restrict__ vis = a.vis;
+  uint8_t* __restrict__ mark = a.mark;
+  const Queues& q = a.q;
+  const int32_t* __restrict__ jstart_base = a.jstart;
+  const int64_t njs = a.njs;
+  const LevelState* __restrict__ st = a.st;
+  const int cbits = a.cbits;
+  const MarkPolicy& mp = a.mp;
+  const int hw = a.hw;
+  uint32_t* __restrict__ hot_new = a.hot_new;
+  const int64_t n = a.n;
+  const int probe = a.probe;
+  uint32_t* s_hot = reinterpret_cast<uint32_t*>(s_lds);
+  uint32_t (*s_starts)[kTileJ / 32] =
+      reinterpret_cast<uint32_t (*)[kTileJ / 32]>(s_lds + kHotWordsMax * 4);
 
   const int k = st->k_expand;
   const int kin = k - 1;
@@ -161,7 +183,7 @@ __global__ __launch_bounds__(kMarkBlock) void k_expand_mark(
   const unsigned long long cin = st->ctr[kin % 3];
   const int64_t F = (int64_t)(cin & cmask);
   const int64_t T = (int64_t)(cin >> cbits);
-  if (F == 0 || !mark_level(cin, cbits, mp) || st->pull) return;   // push levels only
+  if (F == 0 || !mark_level(cin, cbits, mp)) return;
   const int tid = threadIdx.x;
   for (int i = tid; i < hw; i += kMarkBlock) s_hot[i] = vis[i];
   __syncthreads();
@@ -260,12 +282,8 @@ int mark_expand_grid(int device) {
   return cus * std::min(occ, 1);
 }
 
-void mark_expand_launch(int grid, hipStream_t s, const int32_t* col, const uint32_t* vis,
-                        uint8_t* mark, const Queues& q, const int32_t* jstart_base, int64_t njs,
-                        const LevelState* st, int cbits, const MarkPolicy& mp, int hw,
-                        uint32_t* hot_new, int64_t n, int probe) {
-  k_expand_mark<<<grid, kMarkBlock, 0, s>>>(col, vis, mark, q, jstart_base, njs, st, cbits, mp, hw,
-                                            hot_new, n, probe);
+void mark_expand_launch(int grid, hipStream_t s, const MarkArgs& a) {
+  k_expand_mark<<<grid, kMarkBlock, 0, s>>>(a);
 }
 
 }  // namespace bfsi

@@ -1,0 +1,336 @@
+// Search helpers shared by the level kernels of bfs_csr.hip (finish,
+// resolve) and bfs_mark.hip (the mark expand, which also runs the pull
+// levels): selecting a set bit, the head copy's first step and the rest of
+// the searches for a neighbour one level up, and the pull itself.
+#pragma once
+
+#include "bfs_level.h"
+
+namespace bfsi {
+
+// Position of the r-th (0-based) set bit of x; x has more than r set bits.
+__device__ __forceinline__ int select_bit(uint32_t x, int r) {
+  int pos = 0;
+  int c = __popc(x & 0xFFFFu);
+  if (r >= c) { r -= c; x >>= 16; pos += 16; }
+  c = __popc(x & 0xFFu);
+  if (r >= c) { r -= c; x >>= 8; pos += 8; }
+  c = __popc(x & 0xFu);
+  if (r >= c) { r -= c; x >>= 4; pos += 4; }
+  c = __popc(x & 0x3u);
+  if (r >= c) { r -= c; x >>= 2; pos += 2; }
+  if (r >= (int)(x & 1u)) pos += 1;
+  return pos;
+}
+
+__device__ __forceinline__ bool prev_level(int32_t u, int64_t hotv, const uint32_t* s_prev,
+                                           const uint8_t* __restrict__ mark, uint8_t tprev) {
+  return u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u : mark[u] == tprev;
+}
+
+
+// Dense copy of every vertex's first kHead adjacencies with its degree,
+// (u0, u1, u2, degree), entries past the degree -1. The searches of pull
+// and resolve test a vertex's first neighbours from it, reading it in vertex
+// order (coalesced) instead of one scattered row start per vertex, and read
+// the row itself only when those do not decide.
+constexpr int kHead = 3;
+
+
+// First step of the searches for a neighbour one level up (mark tag tprev,
+// or a bit of the LDS bitmap s_prev below hotv): the first kHead adjacencies
+// of each of the thread's RV vertices, from the head copy. p[t] = the first
+// such neighbour and pos[t] its index (< kHead), or p[t] = -1; deg[t] = the
+// vertex's degree (0 for v[t] < 0). The LDS tests of hot neighbours come
+// first, so mark bytes are read only for the cold ones ahead of a hot hit.
+template <int RV>
+__device__ __forceinline__ void head_step(const int4* __restrict__ head,
+                                          const uint8_t* __restrict__ mark,
+                                          const uint32_t* s_prev, int64_t hotv, uint8_t tprev,
+                                          const int32_t (&v)[RV], int32_t (&p)[RV],
+                                          int (&pos)[RV], int32_t (&deg)[RV]) {
+  int32_t u[RV][kHead];
+#pragma unroll
+  for (int t = 0; t < RV; ++t) {
+    const int4 h = v[t] >= 0 ? head[v[t]] : make_int4(-1, -1, -1, 0);
+    u[t][0] = h.x;
+    u[t][1] = h.y;
+    u[t][2] = h.z;
+    deg[t] = h.w;
+  }
+  int hh[RV];
+#pragma unroll
+  for (int t = 0; t < RV; ++t) {
+    hh[t] = kHead;
+#pragma unroll
+    for (int i = kHead - 1; i >= 0; --i)
+      if (u[t][i] >= 0 && u[t][i] < hotv && ((s_prev[u[t][i] >> 5] >> (u[t][i] & 31)) & 1u))
+        hh[t] = i;
+  }
+  uint8_t cm[RV][kHead];
+#pragma unroll
+  for (int t = 0; t < RV; ++t)
+#pragma unroll
+    for (int i = 0; i < kHead; ++i)
+      cm[t][i] = (i < hh[t] && u[t][i] >= hotv) ? mark[u[t][i]] : (uint8_t)0;
+#pragma unroll
+  for (int t = 0; t < RV; ++t) {
+    p[t] = hh[t] < kHead ? u[t][hh[t] < kHead ? hh[t] : 0] : -1;
+    pos[t] = hh[t];
+#pragma unroll
+    for (int i = kHead - 1; i >= 0; --i)
+      if (i < hh[t] && cm[t][i] == tprev) {
+        p[t] = u[t][i];
+        pos[t] = i;
+      }
+  }
+}
+
+// The rest of the searches head_step left open: for each t with p[t] < 0,
+// the adjacencies [o[t] + kHead, end[t]) of its row in order; p[t] = the
+// first neighbour one level up and at[t] = its position, or at[t] = end[t].
+// Each thread advances its open searches four adjacencies at a time up to
+// kSerialScan; the wave finishes the longer ones together, 64 adjacencies
+// per step, so every lane of the wave must make the call.
+template <int RV>
+__device__ __forceinline__ void first_up_rest(const int32_t* __restrict__ col,
+                                              const uint8_t* __restrict__ mark,
+                                              const uint32_t* s_prev, int64_t hotv, uint8_t tprev,
+                                              int lane, const int32_t (&v)[RV],
+                                              const int64_t (&o)[RV], const int64_t (&end)[RV],
+                                              int32_t (&p)[RV], int64_t (&at)[RV]) {
+#pragma unroll
+  for (int t = 0; t < RV; ++t) at[t] = end[t];
+  // continuation up to kSerialScan adjacencies, four per step, the RV
+  // searches of the thread advancing together (their loads overlap)
+  bool pending[RV];
+  {
+    int64_t e[RV], lim[RV];
+#pragma unroll
+    for (int t = 0; t < RV; ++t) {
+      e[t] = o[t] + kHead;
+      lim[t] = min(end[t], o[t] + (int64_t)kSerialScan);
+    }
+    for (;;) {
+      bool any = false;
+      int32_t w4[RV][4];
+#pragma unroll
+      for (int t = 0; t < RV; ++t) {
+        const bool act = p[t] < 0 && e[t] < lim[t];
+        any |= act;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w4[t][i] = (act && e[t] + i < lim[t]) ? col[e[t] + i] : -1;
+      }
+      if (!any) break;
+      uint8_t m4[RV][4];
+#pragma unroll
+      for (int t = 0; t < RV; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          m4[t][i] = (w4[t][i] >= hotv) ? mark[w4[t][i]] : (uint8_t)0;
+#pragma unroll
+      for (int t = 0; t < RV; ++t) {
+#pragma unroll
+        for (int i = 3; i >= 0; --i) {
+          const int32_t u = w4[t][i];
+          if (u < 0) continue;
+          const bool hit = u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u
+                                    : m4[t][i] == tprev;
+          if (hit) {
+            p[t] = u;
+            at[t] = e[t] + i;
+          }
+        }
+        e[t] += 4;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < RV; ++t)
+      pending[t] = v[t] >= 0 && p[t] < 0 && end[t] - o[t] > kSerialScan;
+  }
+  // the wave scans the rest of each long adjacency list together
+#pragma unroll
+  for (int t = 0; t < RV; ++t) {
+    for (;;) {
+      const unsigned long long pend = wave_ballot(pending[t]);
+      if (!pend) break;
+      const int leader = __ffsll((long long)pend) - 1;
+      const int64_t lo = shfl_ll(o[t] + kSerialScan, leader);
+      const int64_t hi = shfl_ll(end[t], leader);
+      int32_t found = -1;
+      int64_t fat = hi;
+      for (int64_t e0 = lo; e0 < hi; e0 += 64) {
+        const int64_t e = e0 + lane;
+        int32_t uu = 0;
+        bool hit = false;
+        if (e < hi) {
+          uu = col[e];
+          hit = prev_level(uu, hotv, s_prev, mark, tprev);
+        }
+        const unsigned long long hb = wave_ballot(hit);
+        if (hb) {
+          const int src = __ffsll((long long)hb) - 1;
+          found = __shfl(uu, src, 64);
+          fat = e0 + src;
+          break;
+        }
+      }
+      if (lane == leader) {
+        p[t] = found;
+        at[t] = fat;
+        pending[t] = false;
+      }
+    }
+  }
+}
+
+// pull(k), the product of a level computed by rows: every unvisited vertex
+// of positive degree searches its ascending adjacency list for the first
+// vertex one level up (head_step, first_up_rest), which is its parent; the masked product
+// of section 3.2 restricted to the rows the mask leaves, the same entries
+// as the push. A vertex that finds one gets its parent and level and is
+// marked touched (byte 1) for finish(k). Each wave takes 64 words of the
+// visited bitmap (2048 vertices), lists their unvisited vertices in LDS and
+// hands them to its lanes RV at a time, so the searches fill the wave.
+// It runs inside the mark expand's launch (bfs_mark.hip), one 1024-thread
+// workgroup per CU, on that kernel's LDS.
+constexpr int kPullBlock = 1024;
+// hot prefix staged by the pull: 144 KiB of bits plus 8 KiB of wave lists
+constexpr int kPullHotWords = 36864;
+constexpr int kPullLdsBytes =
+    kPullHotWords * 4 + 2 * (kPullBlock / 64) * 64 * 4 + 4 * (kPullBlock / 64) * 8;
+// searches per thread
+constexpr int kPullRV = 2;
+
+__device__ __forceinline__ void pull_body(
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+    const int4* __restrict__ head,
+    const uint32_t* __restrict__ vis, unsigned long long* __restrict__ rpl,
+    uint8_t* __restrict__ mark, LevelState* st, const MarkPolicy& mp,
+    const int32_t* __restrict__ inv, int hw, const uint32_t* __restrict__ prev_bits,
+    int64_t n_active, uint8_t* lds) {
+  constexpr int WAVES = kPullBlock / 64;
+  uint32_t* s_prev = reinterpret_cast<uint32_t*>(lds);
+  int (*s_exw)[64] = reinterpret_cast<int (*)[64]>(lds + kPullHotWords * 4);
+  uint32_t (*s_m)[64] = reinterpret_cast<uint32_t (*)[64]>(lds + kPullHotWords * 4 + WAVES * 256);
+  unsigned long long (*s_red)[WAVES] = reinterpret_cast<unsigned long long (*)[WAVES]>(
+      lds + kPullHotWords * 4 + 2 * WAVES * 256);
+  const int k = st->k_fold;
+  const uint8_t tprev = level_tag(k - 1);
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wid = tid >> 6;
+  // the hot prefix goes to LDS when the unvisited vertices' adjacencies
+  // (what the searches read at most) number at least 4 per staged vertex
+  const int hwp = min(hw, kPullHotWords);
+  const unsigned long long seen = st->edges;
+  const unsigned long long rest =
+      (unsigned long long)mp.nnz > seen ? (unsigned long long)mp.nnz - seen : 0ull;
+  const int64_t hotv = rest >= ((unsigned long long)hwp << 7) ? ((int64_t)hwp << 5) : 0;
+  if (hotv)
+    for (int i = tid; i < hwp; i += kPullBlock) s_prev[i] = prev_bits[i];
+  __syncthreads();
+  const int64_t nw = (n_active + 31) >> 5;
+  const int64_t nchunks = (nw + 63) >> 6;
+  const int64_t nwaves = (int64_t)gridDim.x * WAVES;
+  unsigned long long my_cand = 0, my_edges = 0, my_found = 0, my_fdeg = 0;
+  for (int64_t c = (int64_t)blockIdx.x * WAVES + wid; c < nchunks; c += nwaves) {
+    const int64_t w = (c << 6) + lane;
+    uint32_t m = 0u;
+    if (w < nw) {
+      m = ~vis[w];
+      const int64_t left = n_active - (w << 5);   // >= 1 for w < nw
+      if (left < 32) m &= (1u << left) - 1u;
+    }
+    const int cnt = __popc(m);
+    const int incl = (int)wave_incl_scan((long long)cnt);
+    const int total = __shfl(incl, 63, 64);
+    s_exw[wid][lane] = incl - cnt;
+    s_m[wid][lane] = m;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int r = 0; r < total; r += 64 * kPullRV) {
+      int32_t v[kPullRV], p[kPullRV], deg[kPullRV];
+      int pos[kPullRV];
+      int64_t o[kPullRV], end[kPullRV], at[kPullRV];
+#pragma unroll
+      for (int t = 0; t < kPullRV; ++t) {
+        const int i = r + t * 64 + lane;
+        v[t] = -1;
+        if (i < total) {
+          int lo = 0;   // last lane whose list starts at or before i
+#pragma unroll
+          for (int step = 32; step; step >>= 1)
+            if (lo + step <= 63 && s_exw[wid][lo + step] <= i) lo += step;
+          v[t] = (int32_t)((((c << 6) + lo) << 5) + select_bit(s_m[wid][lo], i - s_exw[wid][lo]));
+        }
+      }
+      head_step<kPullRV>(head, mark, s_prev, hotv, tprev, v, p, pos, deg);
+      // rows are read only for the searches the head copy left open
+      bool in_head[kPullRV];
+#pragma unroll
+      for (int t = 0; t < kPullRV; ++t) {
+        in_head[t] = p[t] >= 0;
+        o[t] = 0;
+        end[t] = 0;
+        if (v[t] >= 0 && p[t] < 0 && deg[t] > kHead) {
+          o[t] = off[v[t]];
+          end[t] = o[t] + deg[t];
+        }
+      }
+      first_up_rest<kPullRV>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
+#pragma unroll
+      for (int t = 0; t < kPullRV; ++t) {
+        if (v[t] < 0) continue;
+        my_cand += deg[t] > 0;   // vertices of degree 0 have nothing to search
+        my_edges += in_head[t] ? (unsigned long long)(pos[t] + 1)
+                               : (p[t] >= 0 ? (unsigned long long)(at[t] - o[t] + 1)
+                                            : (unsigned long long)deg[t]);
+        if (p[t] < 0) continue;
+        const int32_t pc = inv ? inv[p[t]] : p[t];
+        rpl[v[t]] = ((unsigned long long)k << 32) | (uint32_t)pc;
+        mark[v[t]] = 1;
+        ++my_found;
+        my_fdeg += (unsigned long long)deg[t];
+      }
+    }
+    // the wave's lists are rewritten by its next chunk
+    __builtin_amdgcn_wave_barrier();
+  }
+  // statistics: candidates and examined adjacencies of the level
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    my_cand += __shfl_xor(my_cand, d, 64);
+    my_edges += __shfl_xor(my_edges, d, 64);
+    my_found += __shfl_xor(my_found, d, 64);
+    my_fdeg += __shfl_xor(my_fdeg, d, 64);
+  }
+  if (lane == 0) {
+    s_red[0][wid] = my_cand;
+    s_red[1][wid] = my_edges;
+    s_red[2][wid] = my_found;
+    s_red[3][wid] = my_fdeg;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long a = 0, b = 0, f = 0, fd = 0;
+    for (int x = 0; x < WAVES; ++x) {
+      a += s_red[0][x];
+      b += s_red[1][x];
+      f += s_red[2][x];
+      fd += s_red[3][x];
+    }
+    if (f) {
+      atomicAdd(&st->pull_found, f);
+      atomicAdd(&st->pull_found_edges, fd);
+    }
+    if (b) atomicAdd(&st->pull_edges, b);
+    if (k < kLevelHist && a) {
+      atomicAdd(&st->hist_pc[k], a);
+      atomicAdd(&st->hist_pe[k], b);
+    }
+  }
+}
+
+}  // namespace bfsi

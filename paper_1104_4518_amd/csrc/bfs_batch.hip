@@ -98,28 +98,33 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   std::vector<int64_t> off((size_t)std::min<int64_t>(n + 1, 1 << 22));
   const int64_t probe = (int64_t)off.size() - 1;
   BFS_HIP(hipMemcpy(off.data(), g->csr.off, off.size() * 8, hipMemcpyDeviceToHost));
+  // roots like a user's: vertices of positive degree at seeded positions
+  // (SplitMix64 of the attempt number), not the hubs, whose first levels
+  // are unlike a typical root's
   std::vector<int32_t> cand;
-  for (int64_t v = 0; v < probe; ++v)
+  for (uint64_t i = 1; cand.size() < 4 && i <= 4096 && probe > 0; ++i) {
+    uint64_t z = i * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const int64_t v = (int64_t)(z % (uint64_t)probe);
     if (off[(size_t)v + 1] > off[(size_t)v]) cand.push_back((int32_t)v);
-  std::partial_sort(cand.begin(), cand.begin() + std::min<size_t>(3, cand.size()), cand.end(),
-                    [&](int32_t a, int32_t b) {
-                      return off[(size_t)a + 1] - off[(size_t)a] >
-                             off[(size_t)b + 1] - off[(size_t)b];
-                    });
-  cand.resize(std::min<size_t>(3, cand.size()));
+  }
   if (cand.empty()) cand.push_back(0);
   std::lock_guard<std::mutex> run_lk(g->run_mu);
   const bfs_options_t saved = g->opt;
   const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   double best = 1e30;
-  int best_grid = cus * 8, best_batch = 4, best_minf = 4096;
+  int best_grid = cus * 8, best_batch = 4, best_minf = 4096, best_alpha = 14;
   int rc = BFS_OK;
   for (int per_cu : {2, 4, 8}) {
-    for (int batch : {2, 4, 8}) {
-      for (int minf : {1024, 4096, 16384}) {
+    for (int batch : {4, 8}) {
+      for (int minf : {1024, 4096, 16384})
+      for (int alpha : {4, 14, 40}) {
         g->opt.grid_blocks = cus * per_cu;
         g->opt.batch_levels = batch;
         g->opt.claim_min_frontier = minf;
+        g->opt.pull_alpha = alpha;
         rc = csr_run(g, cand[0], parent, level, nullptr, true);   // warm
         if (rc != BFS_OK) break;
         const auto t0 = std::chrono::steady_clock::now();
@@ -134,6 +139,7 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
           best_grid = g->opt.grid_blocks;
           best_batch = batch;
           best_minf = minf;
+          best_alpha = alpha;
         }
       }
       if (rc != BFS_OK) break;
@@ -147,8 +153,10 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   g->opt.grid_blocks = best_grid;
   g->opt.batch_levels = best_batch;
   g->opt.claim_min_frontier = best_minf;
+  g->opt.pull_alpha = best_alpha;
   std::ostringstream o;
-  o << "grid=" << best_grid << " batch=" << best_batch << " min_frontier=" << best_minf;
+  o << "grid=" << best_grid << " batch=" << best_batch << " min_frontier=" << best_minf
+    << " pull_alpha=" << best_alpha;
   *result = o.str();
   return BFS_OK;
 }
@@ -317,13 +325,15 @@ int bfs_tune(bfs_graph_t* g, const char* cache_path) {
         const size_t bar = line.find(" | ");
         if (bar == std::string::npos || line.substr(0, bar) != key.str()) continue;
         const char* rest = line.c_str() + bar + 3;
-        int grid = 0, batch = 0, minf = 0, sort_max = 0;
+        int grid = 0, batch = 0, minf = 0, alpha = 0, sort_max = 0;
         if (g->kind == kCsr &&
-            std::sscanf(rest, "grid=%d batch=%d min_frontier=%d", &grid, &batch, &minf) == 3 &&
-            grid > 0 && batch > 0 && minf > 0) {
+            std::sscanf(rest, "grid=%d batch=%d min_frontier=%d pull_alpha=%d", &grid, &batch,
+                        &minf, &alpha) == 4 &&
+            grid > 0 && batch > 0 && minf > 0 && (alpha > 0 || alpha == -1)) {
           g->opt.grid_blocks = grid;
           g->opt.batch_levels = batch;
           g->opt.claim_min_frontier = minf;
+          g->opt.pull_alpha = alpha;
           return BFS_OK;
         }
         if (g->kind == kDcsc && std::sscanf(rest, "sort_max=%d", &sort_max) == 1 &&

@@ -63,29 +63,33 @@ namespace {
 // path's 64-bit atomicMin then orders claims by level, then by parent id);
 // k_out writes the caller's parent and level arrays from it at the end.
 // Vertices of degree 0 past n_active are only ever reached as the root.
+//
+// k_init clears the run's state and seeds it with the root (level 0, its
+// own parent, frontier 0 = {root}): parents are the caller's ids; everything
+// else is indexed by the ids of the CSR the level kernels read (degree order
+// when relabelled).
 __global__ void k_init(int64_t n_active, unsigned long long* __restrict__ rpl,
-                       uint32_t* __restrict__ vis, int64_t nwords, uint4* __restrict__ mark) {
+                       uint32_t* __restrict__ vis, int64_t nwords, uint4* __restrict__ mark,
+                       const int64_t* __restrict__ off, int32_t root,
+                       const int32_t* __restrict__ rank, Queues q, int32_t* jstart,
+                       LevelState* st, int cbits) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = i; v < n_active; v += stride) rpl[v] = ~0ull;
+  const int32_t r = rank ? rank[root] : root;
+  const unsigned long long seed = (unsigned long long)(uint32_t)root;   // level 0
+  for (int64_t v = i; v < n_active; v += stride) rpl[v] = v == r ? seed : ~0ull;
   for (int64_t w = i; w < nwords; w += stride) {
-    vis[w] = 0u;
+    const bool rw = w == (r >> 5);
+    vis[w] = rw ? 1u << (r & 31) : 0u;
     if (mark) {
-      mark[2 * w] = make_uint4(0u, 0u, 0u, 0u);
-      mark[2 * w + 1] = make_uint4(0u, 0u, 0u, 0u);
+      uint32_t x[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+      if (rw) x[(r & 31) >> 2] = (uint32_t)level_tag(0) << (8 * (r & 3));
+      mark[2 * w] = make_uint4(x[0], x[1], x[2], x[3]);
+      mark[2 * w + 1] = make_uint4(x[4], x[5], x[6], x[7]);
     }
   }
-}
-
-__global__ void k_seed(const int64_t* __restrict__ off, int32_t root, unsigned long long* rpl,
-                       uint32_t* vis, uint8_t* mark, Queues q, int32_t* jstart,
-                       LevelState* st, int cbits, const int32_t* __restrict__ rank) {
-  // parents are the caller's ids; everything else is indexed by the ids of
-  // the CSR the level kernels read (degree order when relabelled)
-  const int32_t r = rank ? rank[root] : root;
-  rpl[r] = (unsigned long long)(uint32_t)root;   // level 0
-  vis[r >> 5] |= 1u << (r & 31);
-  if (mark) mark[r] = level_tag(0);
+  if (i != 0) return;
+  if (r >= n_active) rpl[r] = seed;
   const int64_t o = off[r];
   const int64_t d = off[r + 1] - o;
   // jstart holds two maps (frontier parity 0 and 1); frontier 0 uses the first
@@ -669,11 +673,23 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
 // The caller's arrays from the level kernels' words: caller id x reads the
 // word of its level-kernel id (a gather: the writes stay coalesced); ids of
 // degree 0 past n_active other than the root were never reached.
+//
+// Workgroups are dealt to the 8 XCDs in turn, so workgroup b works in the
+// (b mod 8)-th eighth of the caller ids: each XCD's L2 then sees one
+// contiguous range, whose reads fall in a few ascending runs of level-kernel
+// ids (the degree order keeps caller order within a degree), and a fetched
+// line serves all of its words there. The grid is a multiple of 8.
+constexpr int kXcds = 8;
+
 __global__ void k_out(int64_t n, const int32_t* __restrict__ rank, int64_t n_active,
                       int32_t root, const unsigned long long* __restrict__ rpl,
                       int32_t* __restrict__ parent, int32_t* __restrict__ level) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += stride) {
+  const int64_t span = (n + kXcds - 1) / kXcds;
+  const int64_t lo = (int64_t)(blockIdx.x % kXcds) * span;
+  const int64_t hi = min(n, lo + span);
+  const int64_t stride = (int64_t)(gridDim.x / kXcds) * blockDim.x;
+  for (int64_t x = lo + (int64_t)(blockIdx.x / kXcds) * blockDim.x + threadIdx.x; x < hi;
+       x += stride) {
     const int64_t r = rank ? rank[x] : x;
     const unsigned long long w = (r < n_active || x == root) ? rpl[r] : ~0ull;
     parent[x] = (int32_t)(uint32_t)w;
@@ -989,15 +1005,15 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     BFS_HIP(hipEventRecord(g->ev[0], s));
   }
   const int64_t n_active = c.relabeled ? c.n_active : c.n;
-  k_init<<<std::max(igrid, 1), ib, 0, s>>>(n_active, c.rpl, c.vis, c.nwords,
-                                           reinterpret_cast<uint4*>(c.mark));
   // the level kernels read the degree-ordered copy when there is one
   const int64_t* koff = c.relabeled ? c.roff : c.off;
   const int32_t* kcol = c.relabeled ? c.rcol : c.col;
   const int32_t* kinv = c.relabeled ? c.inv : nullptr;
   const int32_t* krank = c.relabeled ? c.rank : nullptr;
-  k_seed<<<1, 1, 0, s>>>(koff, root, c.rpl, c.vis, mp.symmetric ? c.mark : nullptr,
-                         q, c.jstart, c.state, c.cbits, krank);
+  k_init<<<std::max(igrid, 1), ib, 0, s>>>(n_active, c.rpl, c.vis, c.nwords,
+                                           mp.symmetric ? reinterpret_cast<uint4*>(c.mark)
+                                                        : nullptr,
+                                           koff, root, krank, q, c.jstart, c.state, c.cbits);
 
   // launch shapes: the claim expand and finish fill the chip with 256-thread
   // workgroups; the mark expand runs one 1024-thread workgroup per CU (its
@@ -1010,7 +1026,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache;
   const int gm = g->opt.grid_blocks > 0 ? std::min(g->opt.grid_blocks, c.hot_slices) : c.hot_slices;
   const int gf = gf_cache;
-  const int gr = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : gr_cache;
+  const int gr = gr_cache;   // one workgroup per CU (its LDS holds the hot bits)
   BFS_HIP(hipGetLastError());
 
   const int batch = g->opt.batch_levels > 0 ? g->opt.batch_levels : 4;
@@ -1138,7 +1154,8 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     }
   }
   g->expand_launches = (int)k;
-  k_out<<<std::max(igrid, 1), ib, 0, s>>>(c.n, krank, n_active, root, c.rpl, d_parent, d_level);
+  const int ogrid = std::max(kXcds, igrid / kXcds * kXcds);
+  k_out<<<ogrid, ib, 0, s>>>(c.n, krank, n_active, root, c.rpl, d_parent, d_level);
   BFS_HIP(hipGetLastError());
   if (prof) BFS_HIP(hipEventRecord(g->ev[1], s));
   if (host_parent)

@@ -17,11 +17,13 @@ def test_tune_csr_choices_cache_and_results(tmp_path):
     say("tune rmat14")
     G.tune(str(cache))
     o = G.get_options()
-    assert o.batch_levels in (2, 4, 8)
+    assert o.batch_levels in (4, 8)
     assert o.claim_min_frontier in (1024, 4096, 16384)
+    assert o.pull_alpha in (4, 14, 40)
     assert o.grid_blocks > 0 and o.grid_blocks % 2 == 0
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and " csr n=16384 " in lines[0] and "min_frontier=" in lines[0]
+    assert "pull_alpha=" in lines[0]
     for r in graphgen.roots(g, 3, 5):
         say(f"tuned rmat14 root {r}")
         assert_bfs_equal(g, G, r)
@@ -29,8 +31,8 @@ def test_tune_csr_choices_cache_and_results(tmp_path):
     G2 = B.Graph.from_csr(g.n, g.off, g.col)
     G2.tune(str(cache))
     o2 = G2.get_options()
-    assert (o2.grid_blocks, o2.batch_levels, o2.claim_min_frontier) == \
-        (o.grid_blocks, o.batch_levels, o.claim_min_frontier)
+    assert (o2.grid_blocks, o2.batch_levels, o2.claim_min_frontier, o2.pull_alpha) == \
+        (o.grid_blocks, o.batch_levels, o.claim_min_frontier, o.pull_alpha)
     assert len(cache.read_text().splitlines()) == 1
 
 

@@ -193,7 +193,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     int32_t* __restrict__ zq, LevelState* st, int cbits, MarkPolicy mp,
     const int32_t* __restrict__ inv, int hw, uint32_t* __restrict__ prev_bits) {
   constexpr int WAVES = BLOCK / 64;
+  // the tile's rows: edge prefix, adjacency start, caller's id
   __shared__ __align__(16) long long s_qe[kTileJ + 1];
+  __shared__ __align__(16) long long s_qo[kTileJ + 1];
+  __shared__ uint32_t s_u[kTileJ + 1];
   __shared__ int32_t s_ov[kTileJ], s_od[kTileJ];
   __shared__ long long s_wc[WAVES], s_wd[WAVES];
   __shared__ unsigned long long s_base;
@@ -258,15 +261,25 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     const int32_t j0 = jstart[w];
     const int32_t j1 = (w + 1 < njt) ? jstart[w + 1] : (int32_t)(F - 1);
     const int R = j1 - j0 + 1;
-    for (int r = tid; r < R; r += BLOCK) s_qe[r] = qe_in[j0 + r];
+    for (int r = tid; r < R; r += BLOCK) {
+      const int32_t uj = qv_in[j0 + r];
+      s_qe[r] = qe_in[j0 + r];
+      s_qo[r] = qo_in[j0 + r];
+      s_u[r] = (uint32_t)(inv ? inv[uj] : uj);   // caller's id of the frontier vertex
+    }
     if (tid == 0) s_cnt = 0;
     __syncthreads();
 
+    // The thread's ITEMS edges advance stage by stage (targets, visited
+    // words, current words, claims, degrees), so the loads of one stage
+    // are in flight together.
+    int32_t vv[ITEMS];
+    unsigned long long key[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int64_t e = e0 + (int64_t)i * BLOCK + tid;
-      bool own = false;
-      int32_t v = 0;
+      vv[i] = -1;
+      key[i] = 0ull;
       if (e < e1) {
         // row of edge e: last r with s_qe[r] <= e (rows are non-empty)
         int lo = 0, hi = R - 1;
@@ -274,22 +287,41 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
           const int mid = (lo + hi + 1) >> 1;
           if (s_qe[mid] <= e) lo = mid; else hi = mid - 1;
         }
-        const int64_t j = j0 + lo;
-        const int32_t uj = qv_in[j];
-        const uint32_t u = (uint32_t)(inv ? inv[uj] : uj);   // caller's id of the frontier vertex
-        v = col[qo_in[j] + (e - s_qe[lo])];
-        if (!((vis[v >> 5] >> (v & 31)) & 1u)) {
-          const unsigned long long key = ((unsigned long long)k << 32) | u;
-          if (rpl[v] > key) {
-            const unsigned long long old = atomicMin(rpl + v, key);
-            own = (old == ~0ull);
-          }
-        }
+        key[i] = ((unsigned long long)k << 32) | s_u[lo];
+        vv[i] = col[s_qo[lo] + (e - s_qe[lo])];
       }
+    }
+    uint32_t vw[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) vw[i] = vv[i] >= 0 ? vis[vv[i] >> 5] : 0xFFFFFFFFu;
+    unsigned long long cur[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+      cur[i] = (vv[i] >= 0 && !((vw[i] >> (vv[i] & 31)) & 1u)) ? rpl[vv[i]] : 0ull;
+    bool own_i[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      own_i[i] = false;
+      if (cur[i] > key[i]) own_i[i] = atomicMin(rpl + vv[i], key[i]) == ~0ull;
+    }
+    int64_t o0[ITEMS], o1[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      o0[i] = 0;
+      o1[i] = 0;
+      if (own_i[i]) {
+        o0[i] = off[vv[i]];
+        o1[i] = off[vv[i] + 1];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const bool own = own_i[i];
+      const int32_t v = vv[i];
       int32_t deg = 0;
       if (own) {
         if (mp.symmetric) mark[v] = level_tag(k);
-        deg = (int32_t)(off[v + 1] - off[v]);
+        deg = (int32_t)(o1[i] - o0[i]);
         ++my_reached;
       }
       const bool enq = own && deg > 0;

@@ -8,13 +8,13 @@ steps of per-root TEPS, with TEPS = (undirected edges of the searched
 component) / (BFS time), in GTEPS.
 
 The JSON line also carries:
-  roofline      the mark-level kernel k_expand_mark (the dominant kernel on
-                R-MAT), which pushes a large frontier's adjacencies or, on a
-                pull level, computes the product by rows: algorithmic bytes
-                per launch / average launch duration, both from HIP events
-                recorded around every launch of it on its stream (one launch
-                per enqueued level; claim levels' launches exit at once and
-                count too)
+  roofline      the level kernel with the most device time in the timed run:
+                k_expand_mark (pushes a large frontier's adjacencies or, on a
+                pull level, computes the product by rows) or k_expand (the
+                claim levels; on mark levels it only builds the hot bitmap):
+                algorithmic bytes per launch / average launch duration, both
+                from HIP events recorded around every launch of it on its
+                stream (one launch per enqueued level, all counted)
   cpu_baseline  the CPU oracle (serial C) timed on a bounded sample of roots
   bfs_roofline_frac  whole-BFS algorithmic bytes / BFS time, per root
   spmspv        the 2D share (2^26 x 2^26 DCSC, 2^24 uniform nonzeros): 200
@@ -75,12 +75,32 @@ def pull_bytes(levels, n_active: int) -> float:
     return total
 
 
+def claim_bytes(levels, hot_words: int) -> float:
+    """Algorithmic bytes of the claim expand's launches of one BFS: per claim
+    level 4 B + 1/8 B per scanned adjacency (the adjacency, the target's
+    visited bit), 20 B per input frontier vertex (its queue entry), 53 B per
+    vertex claimed (its level/parent word read and min, its two offsets,
+    its queue entry, its tag); per mark level the hot bitmap it builds (32 B
+    of tags read, 4 B written per 32 vertices)."""
+    total = 0.0
+    for i, L in enumerate(levels):
+        if L["frontier"] == 0:
+            continue
+        if L["mark"]:
+            total += 36.0 * hot_words
+            continue
+        new = levels[i + 1]["frontier"] if i + 1 < len(levels) else 0
+        total += 4.125 * L["edges"] + 20.0 * L["frontier"] + 53.0 * new
+    return total
+
+
 def bfs_bytes(n: int, edges: int, reached: int) -> float:
     """Whole-BFS algorithmic bytes: 4 A + A/8 + 24 |R| + 8 n + n/4."""
     return 4.125 * edges + 24.0 * reached + 8.0 * n + n / 4.0
 
 
-KERNEL_SOURCES = {"k_expand_mark": ("bfs_mark.hip", "bfs_search.h")}
+KERNEL_SOURCES = {"k_expand_mark": ("bfs_mark.hip", "bfs_search.h"),
+                  "k_expand": ("bfs_csr.hip",)}
 
 
 def profiled_traffic(kernel: str, workload: str):
@@ -148,7 +168,8 @@ def bfs_leg(args, torch, graphgen, B):
     G.tune(args.tune_cache)   # launch shapes and mark-level floor, measured on this graph (untimed)
     opt = G.get_options()
     tuned = {"grid_blocks": opt.grid_blocks, "batch_levels": opt.batch_levels,
-             "claim_min_frontier": opt.claim_min_frontier, "pull_alpha": opt.pull_alpha}
+             "claim_min_frontier": opt.claim_min_frontier, "pull_alpha": opt.pull_alpha,
+             "claim_threshold": opt.claim_threshold}
     log(f"tuned in {time.time() - t_tune:.1f}s: {tuned}")
     G.set_options(profile=1)
     parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
@@ -186,8 +207,10 @@ def bfs_leg(args, torch, graphgen, B):
     # the pull scans the vertices of positive degree of the degree-ordered copy
     # (graphs of 2^20 vertices and more), else all vertices
     n_active = int((deg > 0).sum()) if g.n >= (1 << 20) else g.n
-    exp_bytes = exp_ms = 0.0
+    kb = {"k_expand_mark": 0.0, "k_expand": 0.0}
+    kms = {"k_expand_mark": 0.0, "k_expand": 0.0}
     exp_launches = 0
+    hot_words = min((g.n + 31) // 32, 39936)
     for i, st in enumerate(stats):
         ms = starts[i].elapsed_time(ends[i])
         if st.reached == giant_size:
@@ -196,14 +219,19 @@ def bfs_leg(args, torch, graphgen, B):
             per_root_frac.append(bfs_bytes(g.n, st.edges_traversed, st.reached) /
                                  (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
         # the mark-level kernel: push levels' and pull levels' work
-        exp_bytes += mark_expand_bytes(levels[i]) + pull_bytes(levels[i], n_active)
-        exp_ms += st.mark_ms + st.pull_ms
-        exp_launches += st.expand_launches   # one launch per enqueued level
+        kb["k_expand_mark"] += mark_expand_bytes(levels[i]) + pull_bytes(levels[i], n_active)
+        kms["k_expand_mark"] += st.mark_ms + st.pull_ms
+        # the claim expand: the rest of each level's expand bracket
+        kb["k_expand"] += claim_bytes(levels[i], hot_words)
+        kms["k_expand"] += st.expand_ms - st.mark_ms - st.pull_ms
+        exp_launches += st.expand_launches   # one launch of each per enqueued level
     value = harmonic(per_root_gteps)
-    kern = "k_expand_mark"
+    kern = max(kms, key=lambda x: kms[x])
+    exp_bytes, exp_ms = kb[kern], kms[kern]
     achieved = exp_bytes / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else 0.0
     log(f"timed {args.steps} roots in {wall:.3f}s wall; {value:.2f} GTEPS; {kern} "
-        f"{exp_launches} launches avg {exp_ms / max(exp_launches, 1) * 1e3:.1f} us")
+        f"{exp_launches} launches avg {exp_ms / max(exp_launches, 1) * 1e3:.1f} us "
+        f"(k_expand {kms['k_expand']:.3f} ms, k_expand_mark {kms['k_expand_mark']:.3f} ms)")
     res = {
         "value": value,
         "wall": wall,

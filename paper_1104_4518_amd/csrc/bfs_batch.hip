@@ -115,16 +115,22 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   const bfs_options_t saved = g->opt;
   const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   double best = 1e30;
-  int best_grid = cus * 8, best_batch = 4, best_minf = 4096, best_alpha = 14;
+  int best_grid = cus * 4, best_batch = 4, best_minf = 4096, best_alpha = 14, best_ct = 0;
   int rc = BFS_OK;
-  for (int per_cu : {2, 4, 8}) {
+  // mark-level edge floor: the default (n / 64), or a sixteenth of the
+  // adjacencies (graphs without hubs, where a push level's resolve scans far
+  // for a small frontier's vertices)
+  const int64_t ct16 = std::min<int64_t>(g->csr.nnz / 16, INT32_MAX);
+  for (int per_cu : {2, 4}) {
     for (int batch : {4, 8}) {
       for (int minf : {1024, 4096, 16384})
-      for (int alpha : {4, 14, 40}) {
+      for (int alpha : {4, 14, 40})
+      for (int ct : {0, (int)ct16}) {
         g->opt.grid_blocks = cus * per_cu;
         g->opt.batch_levels = batch;
         g->opt.claim_min_frontier = minf;
         g->opt.pull_alpha = alpha;
+        g->opt.claim_threshold = ct;
         rc = csr_run(g, cand[0], parent, level, nullptr, true);   // warm
         if (rc != BFS_OK) break;
         const auto t0 = std::chrono::steady_clock::now();
@@ -140,6 +146,7 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
           best_batch = batch;
           best_minf = minf;
           best_alpha = alpha;
+          best_ct = ct;
         }
       }
       if (rc != BFS_OK) break;
@@ -154,9 +161,10 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   g->opt.batch_levels = best_batch;
   g->opt.claim_min_frontier = best_minf;
   g->opt.pull_alpha = best_alpha;
+  g->opt.claim_threshold = best_ct;
   std::ostringstream o;
   o << "grid=" << best_grid << " batch=" << best_batch << " min_frontier=" << best_minf
-    << " pull_alpha=" << best_alpha;
+    << " pull_alpha=" << best_alpha << " claim_threshold=" << best_ct;
   *result = o.str();
   return BFS_OK;
 }
@@ -325,15 +333,16 @@ int bfs_tune(bfs_graph_t* g, const char* cache_path) {
         const size_t bar = line.find(" | ");
         if (bar == std::string::npos || line.substr(0, bar) != key.str()) continue;
         const char* rest = line.c_str() + bar + 3;
-        int grid = 0, batch = 0, minf = 0, alpha = 0, sort_max = 0;
+        int grid = 0, batch = 0, minf = 0, alpha = 0, ct = -1, sort_max = 0;
         if (g->kind == kCsr &&
-            std::sscanf(rest, "grid=%d batch=%d min_frontier=%d pull_alpha=%d", &grid, &batch,
-                        &minf, &alpha) == 4 &&
-            grid > 0 && batch > 0 && minf > 0 && (alpha > 0 || alpha == -1)) {
+            std::sscanf(rest, "grid=%d batch=%d min_frontier=%d pull_alpha=%d claim_threshold=%d",
+                        &grid, &batch, &minf, &alpha, &ct) == 5 &&
+            grid > 0 && batch > 0 && minf > 0 && (alpha > 0 || alpha == -1) && ct >= 0) {
           g->opt.grid_blocks = grid;
           g->opt.batch_levels = batch;
           g->opt.claim_min_frontier = minf;
           g->opt.pull_alpha = alpha;
+          g->opt.claim_threshold = ct;
           return BFS_OK;
         }
         if (g->kind == kDcsc && std::sscanf(rest, "sort_max=%d", &sort_max) == 1 &&

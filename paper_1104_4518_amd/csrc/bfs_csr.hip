@@ -157,17 +157,18 @@ __device__ __forceinline__ void map_tiles(int32_t* __restrict__ jstart, long lon
   for (long long w = (e + kTileJ - 1) / kTileJ; w * kTileJ < e + d; ++w) jstart[w] = j;
 }
 
-// Bitmap of the hot prefix's vertices at level k-1 (mark byte = its tag),
-// built by the claim expand's threads at the start of every mark level for
-// the workgroups of k_resolve and k_pull to copy into LDS. No launch of
-// level k changes a tag of level k-1 (they only turn 0 into 1 and 1 into
-// the tag of level k).
-__device__ __forceinline__ void build_prev_bits(const uint8_t* __restrict__ mark, int k, int hw,
+// Bitmap of the vertices at level k-1 (mark byte = its tag), built by the
+// claim expand's threads at the start of every mark level: the searches of
+// resolve and pull test it (8 times denser than the bytes), and their
+// workgroups copy its hot prefix into LDS. No launch of level k changes a
+// tag of level k-1 (they only turn 0 into 1 and 1 into the tag of level k).
+__device__ __forceinline__ void build_prev_bits(const uint8_t* __restrict__ mark, int k,
+                                                int64_t nwords,
                                                 uint32_t* __restrict__ prev_bits) {
   const uint4* __restrict__ mark4 = reinterpret_cast<const uint4*>(mark);
   const uint32_t tp4 = 0x01010101u * level_tag(k - 1);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < hw; i += stride) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords; i += stride) {
     const uint4 a = mark4[2 * i], b = mark4[2 * i + 1];
     const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
     uint32_t bits = 0;
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     const uint32_t* __restrict__ vis, unsigned long long* __restrict__ rpl,
     uint8_t* __restrict__ mark, Queues q, int32_t* __restrict__ jstart_base, int64_t njs,
     int32_t* __restrict__ zq, LevelState* st, int cbits, MarkPolicy mp,
-    const int32_t* __restrict__ inv, int hw, uint32_t* __restrict__ prev_bits) {
+    const int32_t* __restrict__ inv, int64_t nwords, uint32_t* __restrict__ prev_bits) {
   constexpr int WAVES = BLOCK / 64;
   // the tile's rows: edge prefix, adjacency start, caller's id
   __shared__ __align__(16) long long s_qe[kTileJ + 1];
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   }
   if (F == 0) return;
   if (mark_level(cin, cbits, mp)) {
-    build_prev_bits(mark, k, hw, prev_bits);
+    build_prev_bits(mark, k, nwords, prev_bits);
     return;
   }
   const int64_t njt = (T + kTileJ - 1) / kTileJ;   // jstart tiles of this level
@@ -426,9 +427,32 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
     const int64_t F = (int64_t)(c & cmask);
     const int64_t Z = (int64_t)st->zcnt[k % 3];
     const int32_t* __restrict__ qv = q.qv[k & 1];
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + tid; j < F; j += stride) {
-      const int32_t v = qv[j];
-      atomicOr(&vis[v >> 5], 1u << (v & 31));
+    if (mp.symmetric && F * 64 >= n) {
+      // a large new frontier: its vertices carry this level's tag (set by
+      // their claimers), so the words of the bitmap are rebuilt from the
+      // tags instead of one atomic per vertex (vertices three levels up
+      // share the tag and are visited already)
+      const uint4* __restrict__ m4 = reinterpret_cast<const uint4*>(mark);
+      const uint32_t t4 = 0x01010101u * level_tag(k);
+      for (int64_t w = blockIdx.x * (int64_t)blockDim.x + tid; w < nwords; w += stride) {
+        const uint4 a = m4[2 * w], b = m4[2 * w + 1];
+        const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        uint32_t bits = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const uint32_t e = x[i] ^ t4;   // zero bytes = this level's tag
+#pragma unroll
+          for (int byte = 0; byte < 4; ++byte)
+            if (((e >> (8 * byte)) & 0xFFu) == 0u) bits |= 1u << (4 * i + byte);
+        }
+        const uint32_t old = vis[w];
+        if (bits & ~old) vis[w] = old | bits;
+      }
+    } else {
+      for (int64_t j = blockIdx.x * (int64_t)blockDim.x + tid; j < F; j += stride) {
+        const int32_t v = qv[j];
+        atomicOr(&vis[v >> 5], 1u << (v & 31));
+      }
     }
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + tid; j < Z; j += stride) {
       const int32_t v = zq[j];
@@ -646,7 +670,7 @@ __global__ void k_build_head(int64_t n, const int64_t* __restrict__ off,
 __global__ __launch_bounds__(kResolveBlock) void k_resolve(
     const int32_t* __restrict__ col, const int4* __restrict__ head,
     unsigned long long* __restrict__ rpl,
-    const uint8_t* __restrict__ mark, Queues q, const LevelState* __restrict__ st, int cbits,
+    Queues q, const LevelState* __restrict__ st, int cbits,
     MarkPolicy mp, const int32_t* __restrict__ inv, int hw,
     const uint32_t* __restrict__ prev_bits) {
   __shared__ uint32_t s_prev[kHotWordsMax];
@@ -660,7 +684,6 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
   const int32_t* __restrict__ qv = q.qv[k & 1];
   const int64_t* __restrict__ qo = q.qo[k & 1];
   const int64_t* __restrict__ qe = q.qe[k & 1];
-  const uint8_t tprev = level_tag(k - 1);
   const int tid = threadIdx.x;
   const int lane = lane_id();
   // stage the hot prefix (built by the claim expand) only when the
@@ -691,8 +714,8 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(
     }
     int pos[kResolveRV];
     int32_t deg[kResolveRV];
-    head_step<kResolveRV>(head, mark, s_prev, hotv, tprev, v, p, pos, deg);
-    first_up_rest<kResolveRV>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
+    head_step<kResolveRV>(head, prev_bits, s_prev, hotv, v, p, pos, deg);
+    first_up_rest<kResolveRV>(col, prev_bits, s_prev, hotv, lane, v, o, end, p, at);
 #pragma unroll
     for (int t = 0; t < kResolveRV; ++t) {
       if (v[t] < 0) continue;
@@ -852,7 +875,7 @@ int csr_alloc_workspace(bfs_graph* g) {
     c.hot_words = (int)std::min<int64_t>(std::max<int64_t>(c.nwords, 1), kHotWordsMax);
     c.hot_slices = mark_expand_grid(g->device);
     BFS_HIP(hipMalloc(&c.hot_new, (size_t)c.hot_slices * c.hot_words * 4));
-    BFS_HIP(hipMalloc(&c.prev_bits, (size_t)c.hot_words * 4));
+    BFS_HIP(hipMalloc(&c.prev_bits, (size_t)std::max<int64_t>(c.nwords, 1) * 4));
     // head copy of the rows the searches read (the level kernels' CSR)
     if (!c.relabeled) c.n_active = c.n;
     BFS_HIP(hipMalloc(&c.head, (size_t)std::max<int64_t>(c.n_active, 1) * 16));
@@ -861,7 +884,7 @@ int csr_alloc_workspace(bfs_graph* g) {
     BFS_HIP(hipGetLastError());
     BFS_HIP(hipDeviceSynchronize());
     g->device_bytes += std::max<int64_t>(c.n_active, 1) * 16;
-    g->device_bytes += (int64_t)c.hot_words * 4;
+    g->device_bytes += std::max<int64_t>(c.nwords, 1) * 4;
     g->device_bytes += (int64_t)c.hot_slices * c.hot_words * 4;
   }
   g->device_bytes += std::max<int64_t>(c.nwords, 1) * 4 + c.n * 52 + c.njstart * 8 +
@@ -1073,7 +1096,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     k_expand<kExpandBlock><<<ge, kExpandBlock, 0, st>>>(koff, kcol, c.vis, c.rpl,
                                                         c.mark, q, c.jstart, c.njstart, c.zq,
                                                         c.state, c.cbits, mp, kinv,
-                                                        c.hot_words, c.prev_bits);
+                                                        c.nwords, c.prev_bits);
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 1], st));
     if (mp.symmetric) {
       MarkArgs a;
@@ -1104,7 +1127,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
                                                         c.nwords, mp, c.hot_words, c.hot_new,
                                                         gm);
     if (mp.symmetric)
-      k_resolve<<<gr, kResolveBlock, 0, st>>>(kcol, c.head, c.rpl, c.mark, q, c.state,
+      k_resolve<<<gr, kResolveBlock, 0, st>>>(kcol, c.head, c.rpl, q, c.state,
                                               c.cbits, mp, kinv, c.hot_words, c.prev_bits);
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
     return BFS_OK;

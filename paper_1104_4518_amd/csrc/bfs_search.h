@@ -23,9 +23,12 @@ __device__ __forceinline__ int select_bit(uint32_t x, int r) {
   return pos;
 }
 
+// Vertex u at level k-1: its bit in the LDS copy of the hot prefix (below
+// hotv) or in the level's bitmap pbits (built from the tags at the start of
+// the level).
 __device__ __forceinline__ bool prev_level(int32_t u, int64_t hotv, const uint32_t* s_prev,
-                                           const uint8_t* __restrict__ mark, uint8_t tprev) {
-  return u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u : mark[u] == tprev;
+                                           const uint32_t* __restrict__ pbits) {
+  return ((u < hotv ? s_prev[u >> 5] : pbits[u >> 5]) >> (u & 31)) & 1u;
 }
 
 
@@ -37,16 +40,16 @@ __device__ __forceinline__ bool prev_level(int32_t u, int64_t hotv, const uint32
 constexpr int kHead = 3;
 
 
-// First step of the searches for a neighbour one level up (mark tag tprev,
-// or a bit of the LDS bitmap s_prev below hotv): the first kHead adjacencies
+// First step of the searches for a neighbour one level up (a bit of the
+// level-(k-1) bitmap pbits, or of its LDS copy s_prev below hotv): the first kHead adjacencies
 // of each of the thread's RV vertices, from the head copy. p[t] = the first
 // such neighbour and pos[t] its index (< kHead), or p[t] = -1; deg[t] = the
 // vertex's degree (0 for v[t] < 0). The LDS tests of hot neighbours come
-// first, so mark bytes are read only for the cold ones ahead of a hot hit.
+// first, so bitmap words are read only for the cold ones ahead of a hot hit.
 template <int RV>
 __device__ __forceinline__ void head_step(const int4* __restrict__ head,
-                                          const uint8_t* __restrict__ mark,
-                                          const uint32_t* s_prev, int64_t hotv, uint8_t tprev,
+                                          const uint32_t* __restrict__ pbits,
+                                          const uint32_t* s_prev, int64_t hotv,
                                           const int32_t (&v)[RV], int32_t (&p)[RV],
                                           int (&pos)[RV], int32_t (&deg)[RV]) {
   int32_t u[RV][kHead];
@@ -67,19 +70,19 @@ __device__ __forceinline__ void head_step(const int4* __restrict__ head,
       if (u[t][i] >= 0 && u[t][i] < hotv && ((s_prev[u[t][i] >> 5] >> (u[t][i] & 31)) & 1u))
         hh[t] = i;
   }
-  uint8_t cm[RV][kHead];
+  uint32_t cw[RV][kHead];
 #pragma unroll
   for (int t = 0; t < RV; ++t)
 #pragma unroll
     for (int i = 0; i < kHead; ++i)
-      cm[t][i] = (i < hh[t] && u[t][i] >= hotv) ? mark[u[t][i]] : (uint8_t)0;
+      cw[t][i] = (i < hh[t] && u[t][i] >= hotv) ? pbits[u[t][i] >> 5] : 0u;
 #pragma unroll
   for (int t = 0; t < RV; ++t) {
     p[t] = hh[t] < kHead ? u[t][hh[t] < kHead ? hh[t] : 0] : -1;
     pos[t] = hh[t];
 #pragma unroll
     for (int i = kHead - 1; i >= 0; --i)
-      if (i < hh[t] && cm[t][i] == tprev) {
+      if (i < hh[t] && ((cw[t][i] >> (u[t][i] & 31)) & 1u)) {
         p[t] = u[t][i];
         pos[t] = i;
       }
@@ -94,8 +97,8 @@ __device__ __forceinline__ void head_step(const int4* __restrict__ head,
 // per step, so every lane of the wave must make the call.
 template <int RV>
 __device__ __forceinline__ void first_up_rest(const int32_t* __restrict__ col,
-                                              const uint8_t* __restrict__ mark,
-                                              const uint32_t* s_prev, int64_t hotv, uint8_t tprev,
+                                              const uint32_t* __restrict__ pbits,
+                                              const uint32_t* s_prev, int64_t hotv,
                                               int lane, const int32_t (&v)[RV],
                                               const int64_t (&o)[RV], const int64_t (&end)[RV],
                                               int32_t (&p)[RV], int64_t (&at)[RV]) {
@@ -122,20 +125,19 @@ __device__ __forceinline__ void first_up_rest(const int32_t* __restrict__ col,
         for (int i = 0; i < 4; ++i) w4[t][i] = (act && e[t] + i < lim[t]) ? col[e[t] + i] : -1;
       }
       if (!any) break;
-      uint8_t m4[RV][4];
+      uint32_t m4[RV][4];
 #pragma unroll
       for (int t = 0; t < RV; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          m4[t][i] = (w4[t][i] >= hotv) ? mark[w4[t][i]] : (uint8_t)0;
+          m4[t][i] = (w4[t][i] >= hotv) ? pbits[w4[t][i] >> 5] : 0u;
 #pragma unroll
       for (int t = 0; t < RV; ++t) {
 #pragma unroll
         for (int i = 3; i >= 0; --i) {
           const int32_t u = w4[t][i];
           if (u < 0) continue;
-          const bool hit = u < hotv ? ((s_prev[u >> 5] >> (u & 31)) & 1u) != 0u
-                                    : m4[t][i] == tprev;
+          const bool hit = ((u < hotv ? s_prev[u >> 5] : m4[t][i]) >> (u & 31)) & 1u;
           if (hit) {
             p[t] = u;
             at[t] = e[t] + i;
@@ -165,7 +167,7 @@ __device__ __forceinline__ void first_up_rest(const int32_t* __restrict__ col,
         bool hit = false;
         if (e < hi) {
           uu = col[e];
-          hit = prev_level(uu, hotv, s_prev, mark, tprev);
+          hit = prev_level(uu, hotv, s_prev, pbits);
         }
         const unsigned long long hb = wave_ballot(hit);
         if (hb) {
@@ -216,7 +218,6 @@ __device__ __forceinline__ void pull_body(
   unsigned long long (*s_red)[WAVES] = reinterpret_cast<unsigned long long (*)[WAVES]>(
       lds + kPullHotWords * 4 + 2 * WAVES * 256);
   const int k = st->k_fold;
-  const uint8_t tprev = level_tag(k - 1);
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wid = tid >> 6;
@@ -266,7 +267,7 @@ __device__ __forceinline__ void pull_body(
           v[t] = (int32_t)((((c << 6) + lo) << 5) + select_bit(s_m[wid][lo], i - s_exw[wid][lo]));
         }
       }
-      head_step<kPullRV>(head, mark, s_prev, hotv, tprev, v, p, pos, deg);
+      head_step<kPullRV>(head, prev_bits, s_prev, hotv, v, p, pos, deg);
       // rows are read only for the searches the head copy left open
       bool in_head[kPullRV];
 #pragma unroll
@@ -279,7 +280,7 @@ __device__ __forceinline__ void pull_body(
           end[t] = o[t] + deg[t];
         }
       }
-      first_up_rest<kPullRV>(col, mark, s_prev, hotv, tprev, lane, v, o, end, p, at);
+      first_up_rest<kPullRV>(col, prev_bits, s_prev, hotv, lane, v, o, end, p, at);
 #pragma unroll
       for (int t = 0; t < kPullRV; ++t) {
         if (v[t] < 0) continue;

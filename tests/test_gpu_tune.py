@@ -23,7 +23,8 @@ def test_tune_csr_choices_cache_and_results(tmp_path):
     assert o.grid_blocks > 0 and o.grid_blocks % 2 == 0
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and " csr n=16384 " in lines[0] and "min_frontier=" in lines[0]
-    assert "pull_alpha=" in lines[0]
+    assert "pull_alpha=" in lines[0] and "claim_threshold=" in lines[0]
+    assert o.claim_threshold in (0, g.nnz // 16)
     for r in graphgen.roots(g, 3, 5):
         say(f"tuned rmat14 root {r}")
         assert_bfs_equal(g, G, r)
@@ -31,8 +32,9 @@ def test_tune_csr_choices_cache_and_results(tmp_path):
     G2 = B.Graph.from_csr(g.n, g.off, g.col)
     G2.tune(str(cache))
     o2 = G2.get_options()
-    assert (o2.grid_blocks, o2.batch_levels, o2.claim_min_frontier, o2.pull_alpha) == \
-        (o.grid_blocks, o.batch_levels, o.claim_min_frontier, o.pull_alpha)
+    assert (o2.grid_blocks, o2.batch_levels, o2.claim_min_frontier, o2.pull_alpha,
+            o2.claim_threshold) == \
+        (o.grid_blocks, o.batch_levels, o.claim_min_frontier, o.pull_alpha, o.claim_threshold)
     assert len(cache.read_text().splitlines()) == 1
 
 

@@ -739,16 +739,33 @@ constexpr int kXcds = 8;
 __global__ void k_out(int64_t n, const int32_t* __restrict__ rank, int64_t n_active,
                       int32_t root, const unsigned long long* __restrict__ rpl,
                       int32_t* __restrict__ parent, int32_t* __restrict__ level) {
+  constexpr int U = 4;   // ids per thread per step, their loads in flight together
   const int64_t span = (n + kXcds - 1) / kXcds;
   const int64_t lo = (int64_t)(blockIdx.x % kXcds) * span;
   const int64_t hi = min(n, lo + span);
-  const int64_t stride = (int64_t)(gridDim.x / kXcds) * blockDim.x;
-  for (int64_t x = lo + (int64_t)(blockIdx.x / kXcds) * blockDim.x + threadIdx.x; x < hi;
-       x += stride) {
-    const int64_t r = rank ? rank[x] : x;
-    const unsigned long long w = (r < n_active || x == root) ? rpl[r] : ~0ull;
-    parent[x] = (int32_t)(uint32_t)w;
-    if (level) level[x] = (int32_t)(uint32_t)(w >> 32);
+  const int64_t bstride = (int64_t)(gridDim.x / kXcds) * blockDim.x;
+  for (int64_t x0 = lo + (int64_t)(blockIdx.x / kXcds) * blockDim.x * U + threadIdx.x; x0 < hi;
+       x0 += bstride * U) {
+    int64_t r[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      const int64_t x = x0 + (int64_t)i * blockDim.x;
+      r[i] = x < hi ? (rank ? rank[x] : x) : -1;
+    }
+    unsigned long long w[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      const int64_t x = x0 + (int64_t)i * blockDim.x;
+      w[i] = (r[i] >= 0 && (r[i] < n_active || x == root)) ? rpl[r[i]] : ~0ull;
+    }
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      const int64_t x = x0 + (int64_t)i * blockDim.x;
+      if (x < hi) {
+        parent[x] = (int32_t)(uint32_t)w[i];
+        if (level) level[x] = (int32_t)(uint32_t)(w[i] >> 32);
+      }
+    }
   }
 }
 

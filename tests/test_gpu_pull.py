@@ -136,3 +136,23 @@ def test_pull_alpha_validation():
         G.set_options(pull_alpha=-2, cold_probe=2)
     # a rejected call applies none of its fields
     assert G.get_options().cold_probe == 3
+
+
+@pytest.mark.parametrize("kind", ["rmat", "er"])
+def test_large_claim_levels_set_visited_bits_from_tags(kind):
+    """With the mark levels disabled (edge floor 2^30) a symmetric graph's
+    large frontiers are claimed; a claim level that reaches n/64 vertices or
+    more sets the visited bits from its claimers' tags instead of one atomic
+    per vertex. Every level after it must still see exactly the visited set."""
+    g = graphgen.rmat_csr(16, 16, 38) if kind == "rmat" else graphgen.er_csr(16, 16, 38)
+    G = graph_on_device(g)
+    G.set_options(claim_threshold=1 << 30)
+    rng = np.random.default_rng(38)
+    roots = rng.choice(np.nonzero(np.diff(g.off) > 0)[0], 6, replace=False)
+    for r in roots:
+        say(f"{kind}16 claim levels only, root {r}")
+        _, ol = assert_bfs_equal(g, G, int(r))
+        st = G.last_stats()
+        assert st.mark_levels == 0
+        # some level reached at least n/64 vertices
+        assert np.bincount(ol[ol >= 0]).max() * 64 >= g.n

@@ -8,7 +8,8 @@ steps of per-root TEPS, with TEPS = (undirected edges of the searched
 component) / (BFS time), in GTEPS.
 
 The JSON line also carries:
-  roofline      the level kernel with the most device time in the timed run:
+  roofline      the level kernel with the most device time in the timed run
+                (level_kernels: the same figures for both level kernels):
                 k_expand_mark (pushes a large frontier's adjacencies or, on a
                 pull level, computes the product by rows) or k_expand (the
                 claim levels; on mark levels it only builds the hot bitmap):
@@ -258,6 +259,14 @@ def bfs_leg(args, torch, graphgen, B):
             "avg_launch_us": round(exp_ms / max(exp_launches, 1) * 1e3, 3),
             "bytes_per_launch": round(exp_bytes / max(exp_launches, 1), 1),
         },
+        # both level kernels' HIP-event figures (the roofline is the larger)
+        "level_kernels": {
+            k: {"launches": exp_launches,
+                "avg_launch_us": round(kms[k] / max(exp_launches, 1) * 1e3, 3),
+                "bytes_per_launch": round(kb[k] / max(exp_launches, 1), 1),
+                "achieved_gbs": round(kb[k] / (kms[k] * 1e-3) / 1e9, 2) if kms[k] > 0 else 0.0,
+                "traffic": profiled_traffic(k, args.workload)}
+            for k in kb},
         "bfs_roofline_frac": round(harmonic(per_root_frac), 4),
         "ms_per_bfs_p50": round(pct([starts[i].elapsed_time(ends[i]) for i in
                                      range(args.steps)], 50), 4),
@@ -484,6 +493,7 @@ def main() -> int:
         "data": "synthetic",
         "config": res["config"],
         "roofline": res["roofline"],
+        "level_kernels": res["level_kernels"],
         "bfs_roofline_frac": res["bfs_roofline_frac"],
         "ms_per_bfs_p50": res["ms_per_bfs_p50"],
     }

@@ -319,12 +319,13 @@ int bfs_server_destroy(bfs_server_t* s);
 /* ---------------------------------------------------------------- tuning */
 
 /*
- * Autotuner. CSR graph: times BFS from four seeded roots of positive degree
- * under each combination of expand grid (2, 4 workgroups per CU), levels per
- * host check (4, 8), mark-level frontier floor (1024, 4096, 16384),
- * pull_alpha (4, 14, 40) and mark-level edge floor (claim_threshold: the
- * default, or nnz / 16) and keeps the fastest in the handle's options. DCSC share: times both
- * branches of the SpMSpV polyalgorithm (section 4.2: sparse accumulator, or
+ * Autotuner. CSR graph: times BFS from eight seeded roots of positive degree
+ * (the better of two passes) under each combination of expand grid (2, 4
+ * workgroups per CU), levels per host check (4, 8), mark-level frontier floor
+ * (1024, 4096, 16384), pull_alpha (4, 14, 40) and mark-level edge floor
+ * (claim_threshold: the default, or nnz / 16) and keeps the fastest in the
+ * handle's options. DCSC share: times both branches of the SpMSpV
+ * polyalgorithm (section 4.2: sparse accumulator, or
  * the sort-based merge) on sorted random frontiers of 64 to 8192 entries and
  * sets spmspv_sort_max to the largest size where the sort was faster (-1 if
  * never). When cache_path is not NULL the choice is read from / appended to

@@ -184,8 +184,8 @@ __device__ __forceinline__ void build_prev_bits(const uint8_t* __restrict__ mark
 }
 
 // expand(k), claim levels; on a mark level it only does the level's
-// bookkeeping and builds the hot bitmap of level k-1, leaving the edges to
-// k_expand_mark or k_pull.
+// bookkeeping and builds the bitmap of level k-1, leaving the edges to
+// k_expand_mark (push or pull).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_expand(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col,
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   // (marks beyond the hot prefix, the OR of the expand workgroups' slices
   // within it), append them to the next frontier in vertex order, set their
   // visited bits and give them this level's tag. Parents come from k_resolve
-  // after a push, and were set by k_pull on a pull level.
+  // after a push, and were set by the pull on a pull level.
   int32_t* __restrict__ jstart = jstart_base + (int64_t)(k & 1) * njs;
   int32_t* __restrict__ qv_out = q.qv[k & 1];
   int64_t* __restrict__ qo_out = q.qo[k & 1];

@@ -46,17 +46,20 @@ def log(msg: str) -> None:
 
 
 def mark_expand_bytes(levels) -> float:
-    """Algorithmic bytes of the mark-and-resolve expand launches of one BFS,
-    from its per-level record: per scanned adjacency 4 B (the adjacency) +
-    1/8 B (the target's visited bit); per input frontier vertex 16 B (its
-    adjacency start and edge prefix); per vertex the level reaches 1 B (its
-    touch mark)."""
+    """Algorithmic bytes of the push mark levels of one BFS, from its
+    per-level record: per scanned adjacency 4 B (the adjacency) + 1/8 B (the
+    target's visited bit); per input frontier vertex 16 B (its adjacency start
+    and edge prefix); per vertex the level reaches 1 B (its touch mark); and
+    the level's resolve (run by the next launch of the same kernel): per
+    resolved vertex 44 B (its queue entry, head entry and word), per examined
+    adjacency 4 B + 1/8 B."""
     total = 0.0
     for i, L in enumerate(levels):
         if L["mark"] != 1:
             continue
         new = levels[i + 1]["frontier"] if i + 1 < len(levels) else 0
         total += 4.125 * L["edges"] + 16.0 * L["frontier"] + 1.0 * new
+        total += 44.0 * L["pull_candidates"] + 4.125 * L["pull_edges"]
     return total
 
 

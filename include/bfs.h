@@ -210,11 +210,13 @@ typedef struct bfs_level_info {
   int64_t frontier;     /* vertices of frontier k-1 that were expanded */
   int64_t edges;        /* their adjacencies */
   double expand_ms;     /* device time of the level's expand launches (claim, mark, pull) */
-  double mark_ms;       /* the mark expand kernel's share of expand_ms */
-  double finish_ms;     /* device time of its finish and resolve launches */
+  double mark_ms;       /* the mark expand kernel's share of expand_ms (it also resolves the
+                           previous push level's parents) */
+  double finish_ms;     /* device time of its finish launch */
   double pull_ms;       /* the pull kernel's share of expand_ms */
-  int64_t pull_candidates; /* pull levels: unvisited vertices of positive degree (searchers) */
-  int64_t pull_edges;   /* pull levels: adjacencies they examined */
+  int64_t pull_candidates; /* pull levels: unvisited vertices of positive degree (searchers);
+                              push mark levels: vertices whose parent was searched */
+  int64_t pull_edges;   /* the adjacencies those searches examined */
 } bfs_level_info_t;
 
 /*

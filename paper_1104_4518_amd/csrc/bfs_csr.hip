@@ -116,6 +116,8 @@ __global__ void k_init(int64_t n_active, unsigned long long* __restrict__ rpl,
   st->pull_found = 0ull;
   st->pull_found_edges = 0ull;
   st->qskip = 0;
+  st->kind_cur = 0;
+  st->kind_prev = 0;
 }
 
 // Block-wide exclusive scan of (count, degree sum) pairs; returns the
@@ -227,6 +229,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     st->pull = pull;
     st->pull_found = 0ull;
     st->pull_found_edges = 0ull;
+    // the previous level's kind tells this level's mark kernel whether a
+    // push level's resolve is pending (it runs there, see k_expand_mark)
+    st->kind_prev = st->kind_cur;
+    st->kind_cur = F > 0 ? (pull ? 2 : (mark_level(cin, cbits, mp) ? 1 : 0)) : 0;
     if (k < kLevelHist) {
       st->hist[k] = cin;
       st->hist_mark[k] = pull ? 2 : (mark_level(cin, cbits, mp) ? 1 : 0);
@@ -236,7 +242,9 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   }
   if (F == 0) return;
   if (mark_level(cin, cbits, mp)) {
-    build_prev_bits(mark, k, nwords, prev_bits);
+    // level k's bitmap in buffer k & 1: the other buffer still holds level
+    // k-1's, which the pending resolve of level k-1 reads
+    build_prev_bits(mark, k, nwords, prev_bits + (int64_t)(k & 1) * nwords);
     return;
   }
   const int64_t njt = (T + kTileJ - 1) / kTileJ;   // jstart tiles of this level
@@ -464,8 +472,9 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   // mark level: collect the touched vertices one 32-vertex word per thread
   // (marks beyond the hot prefix, the OR of the expand workgroups' slices
   // within it), append them to the next frontier in vertex order, set their
-  // visited bits and give them this level's tag. Parents come from k_resolve
-  // after a push, and were set by the pull on a pull level.
+  // visited bits and give them this level's tag. Parents come from the resolve
+  // (run by the next level's mark kernel) after a push, and were set by the
+  // pull on a pull level.
   int32_t* __restrict__ jstart = jstart_base + (int64_t)(k & 1) * njs;
   int32_t* __restrict__ qv_out = q.qv[k & 1];
   int64_t* __restrict__ qo_out = q.qo[k & 1];
@@ -645,16 +654,6 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   }
 }
 
-// resolve(k), mark levels: the parent of each vertex of the new frontier is
-// its first neighbour one level up (tag of level k-1) in ascending adjacency
-// order, i.e. the minimum-id frontier vertex adjacent to it. Each thread takes
-// RV vertices at once and tests their first adjacencies together from the
-// head copy, then scans their rows on, four at a time up to kSerialScan; the
-// wave finishes the longer searches together, 64 adjacencies per step. For a
-// large frontier the workgroup first turns the tags of the hot prefix into an
-// LDS bitmap of level k-1, so most tests (hub neighbours) stay in LDS.
-constexpr int kResolveBlock = 1024;
-constexpr int kResolveRV = 4;
 
 __global__ void k_build_head(int64_t n, const int64_t* __restrict__ off,
                              const int32_t* __restrict__ col, int4* __restrict__ head) {
@@ -664,64 +663,6 @@ __global__ void k_build_head(int64_t n, const int64_t* __restrict__ off,
     const int64_t d = off[v + 1] - o;
     head[v] = make_int4(d > 0 ? col[o] : -1, d > 1 ? col[o + 1] : -1, d > 2 ? col[o + 2] : -1,
                         (int)d);
-  }
-}
-
-__global__ __launch_bounds__(kResolveBlock) void k_resolve(
-    const int32_t* __restrict__ col, const int4* __restrict__ head,
-    unsigned long long* __restrict__ rpl,
-    Queues q, const LevelState* __restrict__ st, int cbits,
-    MarkPolicy mp, const int32_t* __restrict__ inv, int hw,
-    const uint32_t* __restrict__ prev_bits) {
-  __shared__ uint32_t s_prev[kHotWordsMax];
-  const int k = st->k_fold;
-  const unsigned long long cmask = (1ull << cbits) - 1;
-  const unsigned long long cin = st->ctr[(k - 1) % 3];
-  if ((cin & cmask) == 0 || !mark_level(cin, cbits, mp) || st->pull) return;
-  const unsigned long long c = st->ctr[k % 3];
-  const int64_t F = (int64_t)(c & cmask);
-  const int64_t T = (int64_t)(c >> cbits);
-  const int32_t* __restrict__ qv = q.qv[k & 1];
-  const int64_t* __restrict__ qo = q.qo[k & 1];
-  const int64_t* __restrict__ qe = q.qe[k & 1];
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  // stage the hot prefix (built by the claim expand) only when the
-  // frontier is large enough to repay it
-  const int64_t hotv = F >= ((int64_t)hw << 5) ? ((int64_t)hw << 5) : 0;
-  if (hotv) {
-    for (int i = tid; i < hw; i += kResolveBlock) s_prev[i] = prev_bits[i];
-    __syncthreads();
-  }
-  const int64_t chunk = (int64_t)kResolveBlock * kResolveRV;
-  const int64_t stride = (int64_t)gridDim.x * chunk;
-  for (int64_t base = (int64_t)blockIdx.x * chunk; base < F; base += stride) {
-    int32_t v[kResolveRV], p[kResolveRV];
-    int64_t o[kResolveRV], end[kResolveRV], at[kResolveRV];
-    // queue entries of the RV vertices, loaded together (indices clamped so
-    // the loads need no branch; entries past F are dropped)
-#pragma unroll
-    for (int t = 0; t < kResolveRV; ++t) {
-      const int64_t j = base + t * kResolveBlock + tid;
-      const int64_t jc = j < F ? j : F - 1;
-      const int64_t jn = jc + 1 < F ? jc + 1 : jc;
-      const int32_t vj = qv[jc];
-      const int64_t oj = qo[jc], e0 = qe[jc], e1 = qe[jn];
-      const bool ok = j < F;
-      v[t] = ok ? vj : -1;
-      o[t] = ok ? oj : 0;
-      end[t] = ok ? oj + ((jc + 1 < F ? e1 : T) - e0) : 0;
-    }
-    int pos[kResolveRV];
-    int32_t deg[kResolveRV];
-    head_step<kResolveRV>(head, prev_bits, s_prev, hotv, v, p, pos, deg);
-    first_up_rest<kResolveRV>(col, prev_bits, s_prev, hotv, lane, v, o, end, p, at);
-#pragma unroll
-    for (int t = 0; t < kResolveRV; ++t) {
-      if (v[t] < 0) continue;
-      const int32_t pc = (inv && p[t] >= 0) ? inv[p[t]] : p[t];
-      rpl[v[t]] = ((unsigned long long)k << 32) | (uint32_t)pc;
-    }
   }
 }
 
@@ -892,7 +833,8 @@ int csr_alloc_workspace(bfs_graph* g) {
     c.hot_words = (int)std::min<int64_t>(std::max<int64_t>(c.nwords, 1), kHotWordsMax);
     c.hot_slices = mark_expand_grid(g->device);
     BFS_HIP(hipMalloc(&c.hot_new, (size_t)c.hot_slices * c.hot_words * 4));
-    BFS_HIP(hipMalloc(&c.prev_bits, (size_t)std::max<int64_t>(c.nwords, 1) * 4));
+    // two buffers: level k's and level k-1's (read by the deferred resolve)
+    BFS_HIP(hipMalloc(&c.prev_bits, (size_t)std::max<int64_t>(c.nwords, 1) * 8));
     // head copy of the rows the searches read (the level kernels' CSR)
     if (!c.relabeled) c.n_active = c.n;
     BFS_HIP(hipMalloc(&c.head, (size_t)std::max<int64_t>(c.n_active, 1) * 16));
@@ -901,7 +843,7 @@ int csr_alloc_workspace(bfs_graph* g) {
     BFS_HIP(hipGetLastError());
     BFS_HIP(hipDeviceSynchronize());
     g->device_bytes += std::max<int64_t>(c.n_active, 1) * 16;
-    g->device_bytes += std::max<int64_t>(c.nwords, 1) * 4;
+    g->device_bytes += std::max<int64_t>(c.nwords, 1) * 8;
     g->device_bytes += (int64_t)c.hot_slices * c.hot_words * 4;
   }
   g->device_bytes += std::max<int64_t>(c.nwords, 1) * 4 + c.n * 52 + c.njstart * 8 +
@@ -1091,14 +1033,12 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   // workgroups; the mark expand runs one 1024-thread workgroup per CU (its
   // LDS holds the hot prefix of the visited bitmap)
 
-  static int ge_cache = 0, gf_cache = 0, gr_cache = 0;
+  static int ge_cache = 0, gf_cache = 0;
   if (!ge_cache) ge_cache = grid_for(g->device, (const void*)k_expand<kExpandBlock>, kExpandBlock, 8);
   if (!gf_cache) gf_cache = grid_for(g->device, (const void*)k_finish<kFinishBlock>, kFinishBlock, 4);
-  if (!gr_cache) gr_cache = grid_for(g->device, (const void*)k_resolve, kResolveBlock, 1);
   const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache;
   const int gm = g->opt.grid_blocks > 0 ? std::min(g->opt.grid_blocks, c.hot_slices) : c.hot_slices;
   const int gf = gf_cache;
-  const int gr = gr_cache;   // one workgroup per CU (its LDS holds the hot bits)
   BFS_HIP(hipGetLastError());
 
   const int batch = g->opt.batch_levels > 0 ? g->opt.batch_levels : 4;
@@ -1106,8 +1046,8 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   const bool prof = g->opt.profile > 0;
   const int probe = g->opt.cold_probe == 3 ? 0 : g->opt.cold_probe;
   // One level: its launches; ev_base >= 0 brackets them with events
-  // ev_base .. ev_base + 3 (claim expand or hot bits | mark expand or pull |
-  // finish + resolve).
+  // ev_base .. ev_base + 3 (claim expand or level bitmap | mark expand or
+  // pull, after the previous push level's resolve | finish).
   auto enqueue_level = [&](hipStream_t st, int64_t ev_base) -> int {
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base], st));
     k_expand<kExpandBlock><<<ge, kExpandBlock, 0, st>>>(koff, kcol, c.vis, c.rpl,
@@ -1135,6 +1075,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
       a.prev_bits = c.prev_bits;
       a.n = c.n;
       a.n_active = n_active;
+      a.nwords = c.nwords;
       a.probe = probe;
       mark_expand_launch(gm, st, a);
     }
@@ -1143,9 +1084,6 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
                                                         c.njstart, c.zq, c.state, c.cbits, c.n,
                                                         c.nwords, mp, c.hot_words, c.hot_new,
                                                         gm);
-    if (mp.symmetric)
-      k_resolve<<<gr, kResolveBlock, 0, st>>>(kcol, c.head, c.rpl, q, c.state,
-                                              c.cbits, mp, kinv, c.hot_words, c.prev_bits);
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
     return BFS_OK;
   };
@@ -1162,7 +1100,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     key.grids[0] = ge;
     key.grids[1] = gm;
     key.grids[2] = gf;
-    key.grids[3] = gr;
+    key.grids[3] = 0;
     key.mp_alpha = mp.pull_alpha;
     key.pad = 0;
     if (!c.gexec || std::memcmp(&key, &c.gkey, sizeof(key)) != 0) {

@@ -59,6 +59,10 @@ struct LevelState {
   // level's input counter, known before finish)
   unsigned long long pull_found, pull_found_edges;
   int32_t qskip;   // the last finish built no queue (its successor pulls)
+  // kind of the current and of the previous level: 0 claim (or empty),
+  // 1 push mark level (its resolve runs in the next level's mark kernel),
+  // 2 pull
+  int32_t kind_cur, kind_prev;
   int32_t pad2;
   // input frontier counter of each level (profiling; levels < kLevelHist)
   unsigned long long hist[4096];

@@ -92,7 +92,7 @@ struct MarkArgs {
   int hw;
   uint32_t* hot_new;
   const uint32_t* prev_bits;
-  int64_t n, n_active;
+  int64_t n, n_active, nwords;
   int probe;
 };
 int mark_expand_grid(int device);

@@ -148,16 +148,26 @@ __device__ __forceinline__ void tile_targets(const int32_t* __restrict__ col,
 // denser than the bytes and stays in L2, which pays once most targets are
 // visited. probe = 1 always reads the byte.
 constexpr int kPushLdsBytes = kHotWordsMax * 4 + (kMarkBlock / 64) * (kTileJ / 32) * 4;
-constexpr int kMarkLdsBytes = kPushLdsBytes > kPullLdsBytes ? kPushLdsBytes : kPullLdsBytes;
+constexpr int kResolveLdsBytes = kHotWordsMax * 4 + 2 * (kResolveBlock / 64) * 8;
+constexpr int kMarkLds1 = kPushLdsBytes > kPullLdsBytes ? kPushLdsBytes : kPullLdsBytes;
+constexpr int kMarkLdsBytes = kMarkLds1 > kResolveLdsBytes ? kMarkLds1 : kResolveLdsBytes;
+static_assert(kResolveBlock == kMarkBlock, "the resolve runs in the mark expand's workgroups");
 static_assert(kPullBlock == kMarkBlock, "the pull runs in the mark expand's workgroups");
 
 __global__ __launch_bounds__(kMarkBlock) void k_expand_mark(MarkArgs a) {
   constexpr int WAVES = kMarkBlock / 64;
   constexpr int STEPS = kTileJ / 64;   // edges per lane per tile
   __shared__ __align__(16) uint8_t s_lds[kMarkLdsBytes];
+  const int kl = a.st->k_expand;   // this launch's level
+  // a push level's resolve, deferred to this (the next) level's launch
+  if (a.st->kind_prev == 1) {
+    resolve_body(kl - 1, a.col, a.head, a.rpl, a.q, a.st, a.cbits, a.inv, a.hw,
+                 a.prev_bits + (int64_t)((kl - 1) & 1) * a.nwords, s_lds);
+    __syncthreads();
+  }
   if (a.st->pull) {
-    pull_body(a.off, a.col, a.head, a.vis, a.rpl, a.mark, a.st, a.mp, a.inv, a.hw, a.prev_bits,
-              a.n_active, s_lds);
+    pull_body(a.off, a.col, a.head, a.vis, a.rpl, a.mark, a.st, a.mp, a.inv, a.hw,
+              a.prev_bits + (int64_t)(kl & 1) * a.nwords, a.n_active, s_lds);
     return;
   }
   const int32_t* __restrict__ col = a.col;

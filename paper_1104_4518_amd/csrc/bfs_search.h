@@ -186,6 +186,106 @@ __device__ __forceinline__ void first_up_rest(const int32_t* __restrict__ col,
   }
 }
 
+// resolve(k), push mark levels: the parent of each vertex of level k's new
+// frontier is its first neighbour one level up (level k-1) in ascending
+// adjacency order, i.e. the minimum-id frontier vertex adjacent to it. Each
+// thread takes RV vertices at once (head_step, then first_up_rest). For a
+// large frontier the workgroup first copies the hot prefix of the level-(k-1)
+// bitmap into LDS, so most tests (hub neighbours) stay in LDS. It runs at the
+// start of level k+1's mark kernel (nothing of level k+1 reads or writes what
+// it touches: level k's queue and counter, the level-(k-1) bitmap buffer and
+// the words of level k's vertices), which saves a launch per level; a level
+// that reached vertices is always followed by another launched level.
+constexpr int kResolveBlock = 1024;
+constexpr int kResolveRV = 4;
+
+__device__ __forceinline__ void resolve_body(
+    int k, const int32_t* __restrict__ col, const int4* __restrict__ head,
+    unsigned long long* __restrict__ rpl, const Queues& q, LevelState* st, int cbits,
+    const int32_t* __restrict__ inv, int hw, const uint32_t* __restrict__ pbits,
+    uint8_t* lds) {
+  constexpr int WAVES = kResolveBlock / 64;
+  uint32_t* s_prev = reinterpret_cast<uint32_t*>(lds);
+  unsigned long long (*s_red)[WAVES] =
+      reinterpret_cast<unsigned long long (*)[WAVES]>(lds + kHotWordsMax * 4);
+  const unsigned long long cmask = (1ull << cbits) - 1;
+  const unsigned long long c = st->ctr[k % 3];
+  const int64_t F = (int64_t)(c & cmask);
+  const int64_t T = (int64_t)(c >> cbits);
+  const int32_t* __restrict__ qv = q.qv[k & 1];
+  const int64_t* __restrict__ qo = q.qo[k & 1];
+  const int64_t* __restrict__ qe = q.qe[k & 1];
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wid = tid >> 6;
+  // stage the hot prefix only when the frontier is large enough to repay it
+  const int64_t hotv = F >= ((int64_t)hw << 5) ? ((int64_t)hw << 5) : 0;
+  if (hotv) {
+    for (int i = tid; i < hw; i += kResolveBlock) s_prev[i] = pbits[i];
+    __syncthreads();
+  }
+  unsigned long long my_cand = 0, my_edges = 0;
+  const int64_t chunk = (int64_t)kResolveBlock * kResolveRV;
+  const int64_t stride = (int64_t)gridDim.x * chunk;
+  for (int64_t base = (int64_t)blockIdx.x * chunk; base < F; base += stride) {
+    int32_t v[kResolveRV], p[kResolveRV];
+    int64_t o[kResolveRV], end[kResolveRV], at[kResolveRV];
+    // queue entries of the RV vertices, loaded together (indices clamped so
+    // the loads need no branch; entries past F are dropped)
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t) {
+      const int64_t j = base + t * kResolveBlock + tid;
+      const int64_t jc = j < F ? j : F - 1;
+      const int64_t jn = jc + 1 < F ? jc + 1 : jc;
+      const int32_t vj = qv[jc];
+      const int64_t oj = qo[jc], e0 = qe[jc], e1 = qe[jn];
+      const bool ok = j < F;
+      v[t] = ok ? vj : -1;
+      o[t] = ok ? oj : 0;
+      end[t] = ok ? oj + ((jc + 1 < F ? e1 : T) - e0) : 0;
+    }
+    int pos[kResolveRV];
+    int32_t deg[kResolveRV];
+    head_step<kResolveRV>(head, pbits, s_prev, hotv, v, p, pos, deg);
+    bool in_head[kResolveRV];
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t) in_head[t] = p[t] >= 0;
+    first_up_rest<kResolveRV>(col, pbits, s_prev, hotv, lane, v, o, end, p, at);
+#pragma unroll
+    for (int t = 0; t < kResolveRV; ++t) {
+      if (v[t] < 0) continue;
+      ++my_cand;
+      my_edges += in_head[t] ? (unsigned long long)(pos[t] + 1)
+                             : (p[t] >= 0 ? (unsigned long long)(at[t] - o[t] + 1)
+                                          : (unsigned long long)(end[t] - o[t]));
+      const int32_t pc = (inv && p[t] >= 0) ? inv[p[t]] : p[t];
+      rpl[v[t]] = ((unsigned long long)k << 32) | (uint32_t)pc;
+    }
+  }
+  // statistics of level k: vertices resolved, adjacencies examined
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    my_cand += __shfl_xor(my_cand, d, 64);
+    my_edges += __shfl_xor(my_edges, d, 64);
+  }
+  if (lane == 0) {
+    s_red[0][wid] = my_cand;
+    s_red[1][wid] = my_edges;
+  }
+  __syncthreads();
+  if (tid == 0 && k < kLevelHist) {
+    unsigned long long a = 0, b = 0;
+    for (int x = 0; x < WAVES; ++x) {
+      a += s_red[0][x];
+      b += s_red[1][x];
+    }
+    if (a) {
+      atomicAdd(&st->hist_pc[k], a);
+      atomicAdd(&st->hist_pe[k], b);
+    }
+  }
+}
+
 // pull(k), the product of a level computed by rows: every unvisited vertex
 // of positive degree searches its ascending adjacency list for the first
 // vertex one level up (head_step, first_up_rest), which is its parent; the masked product

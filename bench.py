@@ -84,16 +84,20 @@ def claim_bytes(levels, hot_words: int) -> float:
     level 4 B + 1/8 B per scanned adjacency (the adjacency, the target's
     visited bit), 20 B per input frontier vertex (its queue entry), 53 B per
     vertex claimed (its level/parent word read and min, its two offsets,
-    its queue entry, its tag); per mark level the hot bitmap it builds (32 B
-    of tags read, 4 B written per 32 vertices)."""
+    its queue entry, its tag), or on a large claim level (touch marks) 9 B
+    (its word's min, its touch byte); per mark level the bitmap it builds
+    (32 B of tags read, 4 B written per 32 vertices)."""
     total = 0.0
     for i, L in enumerate(levels):
         if L["frontier"] == 0:
             continue
-        if L["mark"]:
+        if L["mark"] in (1, 2):
             total += 36.0 * hot_words
             continue
         new = levels[i + 1]["frontier"] if i + 1 < len(levels) else 0
+        if L["mark"] == 3:   # large claim level: word min and touch byte per new vertex
+            total += 4.125 * L["edges"] + 20.0 * L["frontier"] + 9.0 * new
+            continue
         total += 4.125 * L["edges"] + 20.0 * L["frontier"] + 53.0 * new
     return total
 

@@ -97,7 +97,9 @@ typedef struct bfs_svec {
 typedef struct bfs_run_stats {
   int32_t depth;             /* largest level assigned (0 for an isolated root) */
   int32_t levels;            /* levels expanded (levels with a non-empty input frontier) */
-  int64_t edges_traversed;   /* adjacencies scanned = sum of degrees of reached vertices */
+  int64_t edges_traversed;   /* sum of the degrees of the reached vertices (twice the
+                                undirected edges of the searched component, the TEPS
+                                numerator); pull levels examine fewer (pull_edges) */
   int64_t reached;           /* vertices with level >= 0 */
   int64_t frontier_total;    /* sum of frontier sizes over all levels */
   int32_t expand_launches;   /* levels enqueued, including empty speculative ones */
@@ -206,7 +208,8 @@ int bfs_last_stats(bfs_graph_t* g, bfs_run_stats_t* st);
 /* One level of the last profiled run. */
 typedef struct bfs_level_info {
   int32_t level;        /* k: the level whose vertices this step discovered */
-  int32_t mark;         /* 1 = mark-and-resolve, 2 = pull (by rows), 0 = atomicMin claims */
+  int32_t mark;         /* 1 = mark-and-resolve, 2 = pull (by rows), 0 = atomicMin claims,
+                           3 = atomicMin claims collected by touch marks (large claim level) */
   int64_t frontier;     /* vertices of frontier k-1 that were expanded */
   int64_t edges;        /* their adjacencies */
   double expand_ms;     /* device time of the level's expand launches (claim, mark, pull) */

@@ -235,12 +235,14 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     st->kind_cur = F > 0 ? (pull ? 2 : (mark_level(cin, cbits, mp) ? 1 : 0)) : 0;
     if (k < kLevelHist) {
       st->hist[k] = cin;
-      st->hist_mark[k] = pull ? 2 : (mark_level(cin, cbits, mp) ? 1 : 0);
+      st->hist_mark[k] = pull ? 2
+                         : (mark_level(cin, cbits, mp) ? 1 : (claim_mark_level(cin, cbits, mp) ? 3 : 0));
       st->hist_pc[k] = 0ull;
       st->hist_pe[k] = 0ull;
     }
   }
   if (F == 0) return;
+  const bool cmark = claim_mark_level(cin, cbits, mp);
   if (mark_level(cin, cbits, mp)) {
     // level k's bitmap in buffer k & 1: the other buffer still holds level
     // k-1's, which the pending resolve of level k-1 reads
@@ -278,6 +280,38 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     }
     if (tid == 0) s_cnt = 0;
     __syncthreads();
+
+    if (cmark) {
+      // every edge to an unvisited target: min into its word, touch byte
+      int32_t vv[ITEMS];
+      unsigned long long key[ITEMS];
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const int64_t e = e0 + (int64_t)i * BLOCK + tid;
+        vv[i] = -1;
+        key[i] = 0ull;
+        if (e < e1) {
+          int lo = 0, hi = R - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_qe[mid] <= e) lo = mid; else hi = mid - 1;
+          }
+          key[i] = ((unsigned long long)k << 32) | s_u[lo];
+          vv[i] = col[s_qo[lo] + (e - s_qe[lo])];
+        }
+      }
+      uint32_t vw[ITEMS];
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) vw[i] = vv[i] >= 0 ? vis[vv[i] >> 5] : 0xFFFFFFFFu;
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i)
+        if (vv[i] >= 0 && !((vw[i] >> (vv[i] & 31)) & 1u)) {
+          atomicMin(rpl + vv[i], key[i]);
+          mark[vv[i]] = 1;
+        }
+      __syncthreads();
+      continue;
+    }
 
     // The thread's ITEMS edges advance stage by stage (targets, visited
     // words, current words, claims, degrees), so the loads of one stage
@@ -428,7 +462,8 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int tid = threadIdx.x;
 
-  if (!mark_level(cin, cbits, mp)) {
+  const bool cmark = claim_mark_level(cin, cbits, mp);
+  if (!mark_level(cin, cbits, mp) && !cmark) {
     // claim level: visited bits of the new frontier and of its out-degree-0
     // vertices
     const unsigned long long c = st->ctr[k % 3];
@@ -523,7 +558,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   if (blockIdx.x == 0 && tid == 0) st->qskip = 0;
   // a pull level marks every vertex it reaches with a byte; the expand
   // workgroups' hot slices belong to the last push level then
-  const int ns = st->pull ? 0 : nslices;
+  const int ns = (st->pull || cmark) ? 0 : nslices;
   unsigned int my_reached = 0;
   for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nwords; base += stride) {
     const int64_t w = base + tid;

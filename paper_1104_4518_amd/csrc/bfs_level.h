@@ -55,6 +55,23 @@ __device__ __forceinline__ bool mark_level(unsigned long long cin, int cbits,
          (long long)(cin & cmask) >= mp.min_vertices;
 }
 
+// A large claim level on a symmetric graph whose frontier holds at least
+// 1/64 of the adjacencies spread over many vertices (at most 128 per
+// frontier vertex on average, so most targets are new and reached once):
+// every edge to an unvisited target does a 64-bit atomicMin whose result is
+// not waited for and stores the touch byte; finish then collects the touched
+// vertices in vertex order as on mark levels, with the parents already
+// final. Saves the per-edge ownership test and appends. A frontier of a few
+// hubs instead reaches each target many times, and there the claim's plain
+// read before the atomic filters most of them.
+__device__ __forceinline__ bool claim_mark_level(unsigned long long cin, int cbits,
+                                                 const MarkPolicy& mp) {
+  const unsigned long long cmask = (1ull << cbits) - 1;
+  const long long F = (long long)(cin & cmask), T = (long long)(cin >> cbits);
+  return mp.symmetric && F > 0 && !mark_level(cin, cbits, mp) && T * 64 >= mp.nnz &&
+         T <= 128 * F;
+}
+
 // Direction of a mark level's product with input counter cin: by rows (pull)
 // once pull_alpha times the frontier's adjacencies reach those of the
 // vertices still unvisited, which the searches read at most; seen = the

@@ -156,3 +156,24 @@ def test_large_claim_levels_set_visited_bits_from_tags(kind):
         assert st.mark_levels == 0
         # some level reached at least n/64 vertices
         assert np.bincount(ol[ol >= 0]).max() * 64 >= g.n
+
+
+def test_claim_level_with_many_new_vertices_from_few_edges():
+    """A star of 2048 leaves beside a dense random part: from the centre,
+    level 1 claims n/32 vertices through only 2048 adjacencies (well under
+    nnz / 64, so not a touch-mark claim level) and sets their visited bits
+    from the tags; the rest of the search must see exactly that set."""
+    n = 1 << 16
+    rng = np.random.default_rng(39)
+    star = [(0, i) for i in range(1, 2049)]
+    a = rng.integers(2049, n, 600000)
+    b = rng.integers(2049, n, 600000)
+    bridge = [(2048, 5000)]
+    g = graphgen.from_edges(n, star + list(zip(a.tolist(), b.tolist())) + bridge)
+    G = graph_on_device(g)
+    G.set_options(claim_threshold=1 << 30, profile=1)
+    for r in (0, 7, 5000):
+        say(f"star + random, root {r}")
+        assert_bfs_equal(g, G, r)
+    info = [L for L in G.level_info() if L["frontier"] > 0]
+    assert all(L["mark"] in (0, 3) for L in info)

@@ -847,6 +847,9 @@ constexpr int kGraphLevels = 16;
 
 int csr_alloc_workspace(bfs_graph* g) {
   CsrDev& c = g->csr;
+  // default grids of the claim expand and the finish on this handle's device
+  c.grid_expand = grid_for(g->device, (const void*)k_expand<kExpandBlock>, kExpandBlock, 8);
+  c.grid_finish = grid_for(g->device, (const void*)k_finish<kFinishBlock>, kFinishBlock, 4);
   c.nwords = (c.n + 31) / 32;
   c.njstart = c.nnz / kTileJ + 2;
   BFS_HIP(hipMalloc(&c.vis, (size_t)std::max<int64_t>(c.nwords, 1) * 4));
@@ -1068,12 +1071,9 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   // workgroups; the mark expand runs one 1024-thread workgroup per CU (its
   // LDS holds the hot prefix of the visited bitmap)
 
-  static int ge_cache = 0, gf_cache = 0;
-  if (!ge_cache) ge_cache = grid_for(g->device, (const void*)k_expand<kExpandBlock>, kExpandBlock, 8);
-  if (!gf_cache) gf_cache = grid_for(g->device, (const void*)k_finish<kFinishBlock>, kFinishBlock, 4);
-  const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : ge_cache;
+  const int ge = g->opt.grid_blocks > 0 ? g->opt.grid_blocks : c.grid_expand;
   const int gm = g->opt.grid_blocks > 0 ? std::min(g->opt.grid_blocks, c.hot_slices) : c.hot_slices;
-  const int gf = gf_cache;
+  const int gf = c.grid_finish;
   BFS_HIP(hipGetLastError());
 
   const int batch = g->opt.batch_levels > 0 ? g->opt.batch_levels : 4;

@@ -114,6 +114,7 @@ struct CsrDev {
   // rank of the vertex by descending degree; each row keeps its adjacencies
   // in ascending original id, mapped to new ids
   int relabeled = 0;
+  int grid_expand = 0, grid_finish = 0;   // default grids on the handle's device
   int64_t n_active = 0;          // symmetric relabelled graphs: every vertex of positive
                                  // degree has a level-kernel id below this (else n)
   int64_t* roff = nullptr;       // n + 1, rows in new order

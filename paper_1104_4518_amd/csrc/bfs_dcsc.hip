@@ -98,7 +98,9 @@ __global__ void k_spmspv_scatter(int64_t fnnz, const int32_t* __restrict__ fidx,
     const int32_t q1 = cp[lo + 1];
     for (int32_t qq = cp[lo]; qq < q1; ++qq) {
       const int32_t r = ir[qq];
-      if (spa_val[r] > key) atomicMin(&spa_val[r], key);
+      // products rarely share a row, so the min is not filtered by a read
+      // of the (large) value array and its result is not waited for
+      atomicMin(&spa_val[r], key);
       const uint32_t bit = 1u << (r & 31);
       if (!(spa_occ[r >> 5] & bit)) atomicOr(&spa_occ[r >> 5], bit);
     }

@@ -1,7 +1,8 @@
-// Search helpers shared by the level kernels of bfs_csr.hip (finish,
-// resolve) and bfs_mark.hip (the mark expand, which also runs the pull
-// levels): selecting a set bit, the head copy's first step and the rest of
-// the searches for a neighbour one level up, and the pull itself.
+// Search helpers shared by the level kernels of bfs_csr.hip (finish) and
+// bfs_mark.hip (the mark-level kernel, which also runs the pull levels and
+// the deferred resolve): selecting a set bit, the head copy's first step and
+// the rest of the searches for a neighbour one level up, the resolve and the
+// pull.
 #pragma once
 
 #include "bfs_level.h"
@@ -41,8 +42,8 @@ constexpr int kHead = 3;
 
 
 // First step of the searches for a neighbour one level up (a bit of the
-// level-(k-1) bitmap pbits, or of its LDS copy s_prev below hotv): the first kHead adjacencies
-// of each of the thread's RV vertices, from the head copy. p[t] = the first
+// level-(k-1) bitmap pbits, or of its LDS copy s_prev below hotv): the first
+// kHead adjacencies of each of the thread's RV vertices, from the head copy. p[t] = the first
 // such neighbour and pos[t] its index (< kHead), or p[t] = -1; deg[t] = the
 // vertex's degree (0 for v[t] < 0). The LDS tests of hot neighbours come
 // first, so bitmap words are read only for the cold ones ahead of a hot hit.

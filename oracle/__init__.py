@@ -177,3 +177,38 @@ def bfs_2d(n: int, R: int, C: int, pr: int, pc: int, shares, root: int):
         level[new] = k
         f = new
     return parent.astype(np.int32), level.astype(np.int32)
+
+
+def bfs_by_rows(n: int, off, col, root: int):
+    """Level-synchronous BFS in which every level evaluates the masked
+    product of section 3.2 by rows of the mask instead of from the frontier:
+    each vertex not yet visited scans its own adjacency list in ascending
+    order and takes the first vertex of the current frontier it meets as its
+    parent. On an undirected graph with ascending rows that vertex is the
+    smallest frontier id adjacent to it, the entry the (select, min) product
+    gives, so the result must equal bfs(). Plain Python loops: small graphs.
+    Returns (parent, level)."""
+    off = np.asarray(off, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    parent = np.full(n, -1, np.int64)
+    level = np.full(n, -1, np.int64)
+    parent[root] = root
+    level[root] = 0
+    k = 0
+    found = True
+    while found:
+        k += 1
+        found = []
+        for v in range(n):
+            if level[v] != -1:
+                continue
+            for u in col[off[v]:off[v + 1]]:
+                if level[u] == k - 1:
+                    parent[v] = u
+                    found.append(v)
+                    break
+        # the level is assigned after all rows are scanned: a vertex found
+        # in this level is not yet a frontier vertex for the others
+        for v in found:
+            level[v] = k
+    return parent.astype(np.int32), level.astype(np.int32)

@@ -52,7 +52,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "GTEPS (harmonic mean over roots) + % HBM roofline; batched p50/p99 latency"
-KERNELS = ("k_expand", "k_expand_mark", "k_finish")
+KERNELS = ("k_expand", "k_expand_mark", "k_finish", "k_small_levels")
 
 
 def log(msg: str) -> None:
@@ -62,7 +62,7 @@ def log(msg: str) -> None:
 # ------------------------------------------------------------- byte counts
 # Algorithmic bytes per level, from a search's per-level record (one dict per
 # launched level: mark = 0 claim, 1 push mark, 2 pull, 3 claim collected by
-# touch marks; frontier/edges = the level's input frontier and its
+# touch marks, 4 claim level run by the device level loop; frontier/edges = the level's input frontier and its
 # adjacencies; pull_candidates/pull_edges = a pull level's searchers and the
 # adjacencies they examined, or a push mark level's resolved vertices and the
 # adjacencies their searches examined). "new" is the next level's input
@@ -90,7 +90,7 @@ def claim_bytes(levels, nwords: int) -> float:
     graph, 32 B of tags read and 4 B written per bitmap word."""
     total = 0.0
     for i, L in enumerate(levels):
-        if L["frontier"] == 0:
+        if L["frontier"] == 0 or L["mark"] == 4:
             continue
         if L["mark"] in (1, 2):
             total += 36.0 * nwords
@@ -141,13 +141,26 @@ def finish_bytes(levels, nwords: int) -> float:
     total = 0.0
     n = nwords * 32
     for i, L in enumerate(levels):
-        if L["frontier"] == 0:
+        if L["frontier"] == 0 or L["mark"] == 4:
             continue
         new = _new(levels, i)
         if L["mark"] == 0:
             total += 36.0 * nwords if new * 64 >= n else 12.0 * new
             continue
         total += 32.0 * nwords + 37.125 * new
+    return total
+
+
+def small_levels_bytes(levels) -> float:
+    """k_small_levels (the device level loop): per level it runs, 4 B + 1/8 B
+    per scanned adjacency (the adjacency, the target's word read as the
+    visited test counts its 1/8 B bit), 20 B per frontier vertex staged (its
+    queue entry), and per vertex claimed 53 B as on a claim level."""
+    total = 0.0
+    for i, L in enumerate(levels):
+        if L["mark"] != 4 or L["frontier"] == 0:
+            continue
+        total += 4.125 * L["edges"] + 20.0 * L["frontier"] + 53.0 * _new(levels, i)
     return total
 
 
@@ -163,7 +176,7 @@ def examined_bytes(levels, n: int, n_active: int) -> float:
     nwords = (n + 31) // 32
     return (claim_bytes(levels, nwords) + mark_expand_bytes(levels)
             + pull_bytes(levels, n_active) + finish_bytes(levels, nwords)
-            + init_out_bytes(n, n_active, nwords))
+            + small_levels_bytes(levels) + init_out_bytes(n, n_active, nwords))
 
 
 def bfs_bytes(n: int, edges: int, reached: int) -> float:
@@ -175,6 +188,7 @@ def bfs_bytes(n: int, edges: int, reached: int) -> float:
 KERNEL_SOURCES = {"k_expand_mark": ("bfs_mark.hip", "bfs_search.h", "bfs_level.h"),
                   "k_expand": ("bfs_csr.hip", "bfs_level.h"),
                   "k_finish": ("bfs_csr.hip", "bfs_level.h"),
+                  "k_small_levels": ("bfs_small.hip", "bfs_level.h"),
                   "k_spmspv_bin": ("bfs_dcsc.hip",),
                   "k_spmspv_reduce": ("bfs_dcsc.hip",)}
 
@@ -275,8 +289,10 @@ def kernel_split(stats, levels, n: int, n_active: int):
         kb["k_expand"] += claim_bytes(lv, nwords)
         kms["k_expand"] += st.expand_ms - st.mark_ms - st.pull_ms
         kb["k_finish"] += finish_bytes(lv, nwords)
-        kms["k_finish"] += sum(L["finish_ms"] for L in lv)
-        launches += st.expand_launches   # one launch of each kernel per enqueued level
+        kms["k_finish"] += st.finish_ms
+        kb["k_small_levels"] += small_levels_bytes(lv)
+        kms["k_small_levels"] += st.small_ms
+        launches += st.expand_launches   # one launch of each kernel per launch group
     out = {}
     for k in KERNELS:
         out[k] = {"launches": launches,
@@ -297,11 +313,16 @@ def bfs_workload(name, args, torch, graphgen, B, np, cpu: bool, steps: int, warm
     G = B.Graph.from_csr(g.n, g.off, g.col, trusted=True, symmetric=True)
     log(f"{name}: resident on device in {time.time() - t1:.1f}s")
     t_tune = time.time()
-    G.tune(args.tune_cache)   # launch shapes and level floors, measured on this graph (untimed)
+    if args.options:
+        # fixed options (e.g. those a tuned run reported), no timing sweep
+        G.set_options(**{k: int(v) for k, v in
+                         (kv.split("=") for kv in args.options.split(",") if kv)})
+    else:
+        G.tune(args.tune_cache)   # launch shapes and level floors, measured here (untimed)
     opt = G.get_options()
     tuned = {"grid_blocks": opt.grid_blocks, "batch_levels": opt.batch_levels,
              "claim_min_frontier": opt.claim_min_frontier, "pull_alpha": opt.pull_alpha,
-             "claim_threshold": opt.claim_threshold}
+             "claim_threshold": opt.claim_threshold, "small_frontier": opt.small_frontier}
     log(f"{name}: tuned in {time.time() - t_tune:.1f}s: {tuned}")
     G.set_options(profile=-1)
     parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
@@ -337,13 +358,13 @@ def bfs_workload(name, args, torch, graphgen, B, np, cpu: bool, steps: int, warm
         levels.append(G.level_info())
     G.set_options(profile=-1)
     torch.cuda.synchronize()
-    kinds = {0: "claim", 1: "push", 2: "pull", 3: "claim-touch"}
+    kinds = {0: "claim", 1: "push", 2: "pull", 3: "claim-touch", 4: "loop"}
     for L in levels[0]:
         log(f"{name} root {roots[0]} level {L['level']:3d} {kinds.get(L['mark'], '?'):11s} "
             f"F={L['frontier']:>9d} T={L['edges']:>11d} searched={L['pull_candidates']:>9d} "
             f"examined={L['pull_edges']:>10d} expand={L['expand_ms'] * 1e3:8.1f}us "
             f"(mark kernel {(L['mark_ms'] + L['pull_ms']) * 1e3:8.1f}us) "
-            f"finish={L['finish_ms'] * 1e3:7.1f}us")
+            f"finish={L['finish_ms'] * 1e3:7.1f}us loop={L['small_ms'] * 1e3:7.1f}us")
 
     deg = np.diff(np.asarray(g.off))
     # the pull scans the vertices of positive degree of the degree-ordered copy
@@ -451,7 +472,7 @@ def spmspv_leg(args, torch, graphgen, B, np):
     out = {"empty_call_p50_us": round(pct(floor, 50), 2)}
     call = 0
     samples = {}
-    for density in (0.0001, 0.001, 0.01, 0.1):
+    for density in [float(x) for x in args.spmspv_densities.split(",")]:
         k = int(density * (1 << 26))
         times, algo, edges_s = [], [], []
         for rep in range(51):
@@ -579,6 +600,24 @@ def mix_leg(torch, graphgen, B, np, nq: int):
     batch_s = time.perf_counter() - t1
     batched = {"gteps": round(m_total / batch_s / 1e9, 4), "seconds": round(batch_s, 4),
                "speedup_vs_plain": round(plain_s / batch_s, 2), "sample_equal": agree(outs)}
+    # each graph class alone: its queries in one batch against the same
+    # queries one at a time on the plain path
+    by_graph = {}
+    for gi, (name, _) in enumerate(specs):
+        idx = [int(i) for i in np.nonzero(qg == gi)[0]]
+        if not idx:
+            continue
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        B.run_batch([devs[gi]] * len(idx), qr[idx], [outs[i][0] for i in idx],
+                    [outs[i][1] for i in idx])
+        torch.cuda.synchronize()
+        bs = time.perf_counter() - t1
+        ps = float(per_class[gi])
+        by_graph[name] = {"queries": len(idx), "plain_s": round(ps, 4), "batched_s": round(bs, 4),
+                          "batched_vs_plain": round(ps / bs, 2) if bs > 0 else None}
+    batched["by_graph"] = by_graph
+    batched["sample_equal_by_graph"] = agree(outs)
     log(f"batched: {batched}")
 
     served = {}
@@ -635,6 +674,11 @@ def main() -> int:
     ap.add_argument("--legs", default="bfs,spmspv,mix",
                     help="comma list of legs to run: bfs, spmspv, mix")
     ap.add_argument("--mix-queries", type=int, default=1024)
+    ap.add_argument("--options", default="",
+                    help="comma list name=value of graph options to set instead of tuning "
+                         "(e.g. the tuned_options of an earlier line), for profiled runs")
+    ap.add_argument("--spmspv-densities", default="0.0001,0.001,0.01,0.1",
+                    help="frontier densities of the SpMSpV leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (3 times), to scale HBM counters")
     args = ap.parse_args()

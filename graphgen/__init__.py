@@ -305,6 +305,19 @@ def config_roots(name: str, g: CSR) -> np.ndarray:
     return roots(g, c["roots"], c["root_seed"])
 
 
+def upper_csr(g: CSR) -> CSR:
+    """Symmetric storage of an undirected graph (storage only): each edge
+    once, in the row of its smaller endpoint, i.e. the entries v > u of every
+    row u, kept in ascending order."""
+    n = g.n
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.off))
+    keep = g.col.astype(np.int64) > src
+    cnt = np.bincount(src[keep], minlength=n)
+    off = np.zeros(n + 1, np.int64)
+    np.cumsum(cnt, out=off[1:])
+    return CSR(n, off, np.ascontiguousarray(g.col[keep]), name=g.name + "_upper")
+
+
 def csr_to_2d(g: CSR, pr: int, pc: int):
     """The p_r x p_c decomposition of a graph's adjacency matrix into DCSC
     shares (storage only). A(v, u) = 1 for each stored adjacency u -> v, so

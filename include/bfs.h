@@ -76,6 +76,19 @@ typedef enum bfs_status {
                                  n >= 2^20 otherwise get for the single-query level kernels
                                  (results are identical either way; the copy costs nnz * 4 +
                                  n * 16 device bytes) */
+#define BFS_UPPER 0x10u       /* CSR: symmetric storage (the paper's closing section): the
+                                 arrays hold each undirected edge once, in the row of its
+                                 smaller endpoint (every adjacency v of row u has v > u, rows
+                                 strictly ascending; checked unless BFS_TRUSTED, else
+                                 BFS_ERR_FORMAT). bfs_run searches the symmetric closure with
+                                 the same results as the full CSR, storing half the
+                                 adjacencies and no degree-ordered copy: each level pushes the
+                                 frontier's stored (larger) neighbours and every unvisited
+                                 vertex not reached that way scans its own row for a frontier
+                                 vertex, so levels read the rows of all unvisited vertices.
+                                 Such graphs run through bfs_run / bfs_run_async / bfs_tune
+                                 and the server's whole-GPU lane; bfs_run_batch rejects them
+                                 (BFS_ERR_UNSUPPORTED). */
 
 /*
  * Sparse vector with device storage, indices strictly ascending (the 2D
@@ -102,7 +115,9 @@ typedef struct bfs_run_stats {
                                 numerator); pull levels examine fewer (pull_edges) */
   int64_t reached;           /* vertices with level >= 0 */
   int64_t frontier_total;    /* sum of frontier sizes over all levels */
-  int32_t expand_launches;   /* levels enqueued, including empty speculative ones */
+  int32_t expand_launches;   /* launch groups enqueued (each: the device level loop for small
+                                frontiers, then one level's kernels), including empty
+                                speculative ones */
   int32_t mark_levels;       /* levels resolved by mark-and-resolve instead of atomicMin */
   double expand_ms;          /* summed device time of the levels' expand launches, claim,
                                 mark and pull kernels (options.profile = 1) */
@@ -112,6 +127,10 @@ typedef struct bfs_run_stats {
   int32_t reserved;
   double pull_ms;            /* the pull kernel's share of expand_ms */
   int64_t pull_edges;        /* adjacencies examined by the pull levels */
+  int32_t small_levels;      /* levels run by the device level loop for small frontiers */
+  int32_t reserved2;
+  double small_ms;           /* device time of the device level loop's launches (profile = 1) */
+  double finish_ms;          /* device time of the levels' finish launches (profile = 1) */
 } bfs_run_stats_t;
 
 /* Run-time tuning knobs of a graph handle (0 = keep the current value). */
@@ -146,6 +165,12 @@ typedef struct bfs_options {
                            frontier) instead of pushing the frontier's adjacencies when
                            pull_alpha * (frontier adjacencies) >= adjacencies of the
                            vertices not yet visited; -1 = never (0 = keep; default 14) */
+  int32_t small_frontier; /* device level loop: claim levels whose frontier holds at most
+                             this many vertices (and at most 16384 adjacencies) run inside one
+                             workgroup, level after level, without host checks or per-level
+                             launches (high-diameter graphs, first and last levels of every
+                             search); at most 8192; -1 = off (0 = keep; default 8192). Not
+                             used for BFS_UPPER graphs */
 } bfs_options_t;
 
 /* ---------------------------------------------------------------- graphs */
@@ -209,7 +234,8 @@ int bfs_last_stats(bfs_graph_t* g, bfs_run_stats_t* st);
 typedef struct bfs_level_info {
   int32_t level;        /* k: the level whose vertices this step discovered */
   int32_t mark;         /* 1 = mark-and-resolve, 2 = pull (by rows), 0 = atomicMin claims,
-                           3 = atomicMin claims collected by touch marks (large claim level) */
+                           3 = atomicMin claims collected by touch marks (large claim level),
+                           4 = atomicMin claims inside the device level loop */
   int64_t frontier;     /* vertices of frontier k-1 that were expanded */
   int64_t edges;        /* their adjacencies */
   double expand_ms;     /* device time of the level's expand launches (claim, mark, pull) */
@@ -220,12 +246,15 @@ typedef struct bfs_level_info {
   int64_t pull_candidates; /* pull levels: unvisited vertices of positive degree (searchers);
                               push mark levels: vertices whose parent was searched */
   int64_t pull_edges;   /* the adjacencies those searches examined */
+  double small_ms;      /* on the first level of a run of the device level loop: that
+                           launch's device time (its levels carry no time of their own) */
 } bfs_level_info_t;
 
 /*
- * Per-level record of the last run made with options.profile = 1, for the
- * first min(capacity, 4096) launched levels (empty trailing levels included,
- * with frontier 0). *count receives the number of launched levels.
+ * Per-level record of the last run, for levels 1 .. min(capacity, 4095, the
+ * level that found the frontier empty); *count receives the number written.
+ * Frontier sizes and kinds are recorded always, device times only when the
+ * run had options.profile = 1 (mode 1).
  */
 int bfs_last_level_info(bfs_graph_t* g, bfs_level_info_t* out, int32_t capacity,
                         int32_t* count);
@@ -236,10 +265,15 @@ int bfs_last_level_info(bfs_graph_t* g, bfs_level_info_t* out, int32_t capacity,
  * emitted for every r whose set is non-empty, rows ascending. Entries of the
  * frontier on empty columns contribute nothing. No visited mask is applied
  * (the owner applies it, Algorithm 3). frontier->idx must be strictly
- * ascending and in [0, ncols) (BFS_ERR_ARG otherwise, checked on device).
- * When out->capacity is too small, returns BFS_ERR_CAPACITY with the
- * required size in out->nnz and writes nothing to out->idx/val.
- * Synchronous on `hip_stream` (reads the output count back).
+ * ascending and in [0, ncols) (BFS_ERR_ARG otherwise, checked on device;
+ * out->idx/val are then left untouched). An empty frontier gives an empty
+ * product without device work. When out->capacity is too small, returns
+ * BFS_ERR_CAPACITY with the required size in out->nnz; out->idx/val then
+ * hold unspecified values in their first capacity entries and nothing is
+ * written past them. The block's accumulator (row bins, pair buffer of nnz
+ * entries, sized at create) is reused by every call on the handle, so calls
+ * on one handle must not overlap. Synchronous on `hip_stream` (reads the
+ * output count back).
  */
 int bfs_spmspv(bfs_graph_t* block, const bfs_svec_t* frontier, bfs_svec_t* out,
                void* hip_stream);
@@ -263,7 +297,8 @@ int bfs_spmspv(bfs_graph_t* block, const bfs_svec_t* frontier, bfs_svec_t* out,
  * neighbour one level up. The shares' run locks are held for the call;
  * their workspace (the SpMSpV accumulators) is used. Synchronous on
  * `hip_stream` (the frontier size is read back every level); the call
- * allocates its own per-run workspace (about 17 n bytes).
+ * allocates its own per-run workspace (about 24 n bytes) and frees it
+ * before returning.
  */
 int bfs_run_2d(bfs_graph_t* const* shares, int32_t pr, int32_t pc, int64_t n, int32_t root,
                int32_t* parent, int32_t* level, void* hip_stream);
@@ -271,11 +306,16 @@ int bfs_run_2d(bfs_graph_t* const* shares, int32_t pr, int32_t pc, int64_t n, in
 /* ---------------------------------------------------------------- batches */
 
 /*
- * Runs `count` independent BFS queries (graphs[i], roots[i]) in one
- * persistent launch (a multi-query kernel with per-query frontiers and level
- * counters). parents[i] (required) and levels[i] (may be NULL) are device
- * arrays of graphs[i]'s n. Results equal those of bfs_run for each query.
- * Synchronous on `hip_stream`.
+ * Runs `count` independent BFS queries (graphs[i], roots[i]): one persistent
+ * launch of a multi-query kernel (one workgroup runs a query to completion,
+ * per-query frontiers and level counters, largest estimated cost first)
+ * takes the queries on graphs below 2^23 adjacencies or of average degree
+ * below 8; queries on larger few-level graphs run one at a time through the
+ * whole-GPU level kernels on a library-owned stream while that launch runs.
+ * parents[i] (required) and levels[i] (may be NULL) are device arrays of
+ * graphs[i]'s n and must not alias. Results equal those of bfs_run for each
+ * query. BFS_UPPER graphs are rejected (BFS_ERR_UNSUPPORTED). Synchronous on
+ * `hip_stream`.
  */
 int bfs_run_batch(int32_t count, bfs_graph_t* const* graphs, const int32_t* roots,
                   int32_t* const* parents, int32_t* const* levels, void* hip_stream);
@@ -325,15 +365,18 @@ int bfs_server_destroy(bfs_server_t* s);
 
 /*
  * Autotuner. CSR graph: times BFS from eight seeded roots of positive degree
- * (the better of two passes) under each combination of expand grid (2, 4
- * workgroups per CU), levels per host check (4, 8), mark-level frontier floor
- * (1024, 4096, 16384), pull_alpha (4, 14, 40) and mark-level edge floor
- * (claim_threshold: the default, or nnz / 16) and keeps the fastest in the
- * handle's options. DCSC share: times both branches of the SpMSpV
- * polyalgorithm (section 4.2: sparse accumulator, or
- * the sort-based merge) on sorted random frontiers of 64 to 8192 entries and
- * sets spmspv_sort_max to the largest size where the sort was faster (-1 if
- * never). When cache_path is not NULL the choice is read from / appended to
+ * (the median of three passes) and tunes, by coordinate descent from the
+ * defaults (two sweeps, a knob at a time), the expand grid (2, 4 workgroups
+ * per CU), levels per host check (4, 8), mark-level frontier floor (4096,
+ * 1024, 16384), pull_alpha (14, 4, 40), mark-level edge floor
+ * (claim_threshold: the default, or nnz / 16) and the device level loop's
+ * frontier limit (small_frontier: 8192, 1024, off); a value replaces the
+ * current one only when it is more than 3% faster, so repeated tuning keeps
+ * the same choice. The result is kept in the handle's options. DCSC share:
+ * times both branches of the SpMSpV polyalgorithm (section 4.2: the binned
+ * accumulator, or the sort-based merge) on sorted random frontiers of 64 to
+ * 8192 entries and sets spmspv_sort_max to the largest size where the sort
+ * was faster by the same margin (-1 if never). When cache_path is not NULL the choice is read from / appended to
  * that text file, one line per device name and graph shape. Results of later
  * runs do not depend on the choice, only their speed. Holds the handle's run
  * lock while timing.

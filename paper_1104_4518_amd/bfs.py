@@ -34,6 +34,7 @@ BFS_DEVICE_PTRS = 0x1
 BFS_TRUSTED = 0x2
 BFS_SYMMETRIC = 0x4
 BFS_NO_RELABEL = 0x8
+BFS_UPPER = 0x10
 
 _NAMES = {v: k for k, v in globals().items() if k.startswith("BFS_ERR_") or k == "BFS_OK"}
 
@@ -56,7 +57,9 @@ class RunStats(ctypes.Structure):
                 ("mark_levels", ctypes.c_int32), ("expand_ms", ctypes.c_double),
                 ("mark_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("pull_levels", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("pull_ms", ctypes.c_double), ("pull_edges", ctypes.c_int64)]
+                ("pull_ms", ctypes.c_double), ("pull_edges", ctypes.c_int64),
+                ("small_levels", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("small_ms", ctypes.c_double), ("finish_ms", ctypes.c_double)]
 
 
 class LevelInfo(ctypes.Structure):
@@ -64,7 +67,8 @@ class LevelInfo(ctypes.Structure):
                 ("frontier", ctypes.c_int64), ("edges", ctypes.c_int64),
                 ("expand_ms", ctypes.c_double), ("mark_ms", ctypes.c_double),
                 ("finish_ms", ctypes.c_double), ("pull_ms", ctypes.c_double),
-                ("pull_candidates", ctypes.c_int64), ("pull_edges", ctypes.c_int64)]
+                ("pull_candidates", ctypes.c_int64), ("pull_edges", ctypes.c_int64),
+                ("small_ms", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
@@ -73,7 +77,7 @@ class Options(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("claim", ctypes.c_int32),
                 ("claim_threshold", ctypes.c_int32), ("claim_min_frontier", ctypes.c_int32),
                 ("cold_probe", ctypes.c_int32), ("spmspv_sort_max", ctypes.c_int32),
-                ("pull_alpha", ctypes.c_int32)]
+                ("pull_alpha", ctypes.c_int32), ("small_frontier", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -204,10 +208,13 @@ class Graph:
     # ---------------------------------------------------------------- create
     @classmethod
     def from_csr(cls, n: int, off, col, trusted: bool = False,
-                 symmetric: Optional[bool] = None, relabel: bool = True) -> "Graph":
+                 symmetric: Optional[bool] = None, relabel: bool = True,
+                 upper: bool = False) -> "Graph":
         """symmetric=True asserts an undirected graph with ascending rows;
         None lets the library check it (unless trusted). relabel=False
-        skips the degree-ordered copy of large graphs."""
+        skips the degree-ordered copy of large graphs. upper=True: the
+        arrays hold each undirected edge once, in the row of its smaller
+        endpoint (BFS_UPPER); the symmetric closure is searched."""
         lib = load()
         dev = _is_device(off)
         if dev != _is_device(col):
@@ -223,6 +230,8 @@ class Graph:
             flags |= BFS_SYMMETRIC
         if not relabel:
             flags |= BFS_NO_RELABEL
+        if upper:
+            flags |= BFS_UPPER
         h = _vp()
         nnz = int(col.shape[0])
         _check(lib.bfs_graph_create_csr(n, nnz, _ptr(off), ob, _ptr(col) if nnz else None, flags,
@@ -271,9 +280,9 @@ class Graph:
 
     def set_options(self, mode=0, batch_levels=0, grid_blocks=0, lds_bitmap=0, profile=0,
                     claim=0, claim_threshold=0, claim_min_frontier=0, cold_probe=0,
-                    spmspv_sort_max=0, pull_alpha=0):
+                    spmspv_sort_max=0, pull_alpha=0, small_frontier=0):
         o = Options(mode, batch_levels, grid_blocks, lds_bitmap, profile, claim, claim_threshold,
-                    claim_min_frontier, cold_probe, spmspv_sort_max, pull_alpha)
+                    claim_min_frontier, cold_probe, spmspv_sort_max, pull_alpha, small_frontier)
         _check(load().bfs_graph_set_options(self.handle, ctypes.byref(o)),
                "bfs_graph_set_options")
 

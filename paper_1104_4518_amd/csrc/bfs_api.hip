@@ -26,6 +26,14 @@ int hip_fail(hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? BFS_ERR_OOM : BFS_ERR_DEVICE;
 }
 
+hipError_t wait_stream(hipStream_t s) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(s);
+    if (e != hipErrorNotReady) return e;
+    __builtin_ia32_pause();
+  }
+}
+
 int csr_widen(const int32_t* d_src32, int64_t n1, int64_t* d_dst, hipStream_t s);
 
 namespace {
@@ -55,6 +63,7 @@ void default_options(bfs_options_t* o) {
   o->cold_probe = 3;
   o->spmspv_sort_max = 512;
   o->pull_alpha = 14;
+  o->small_frontier = 0;
 }
 
 }  // namespace
@@ -126,12 +135,25 @@ int bfs_graph_create_csr(int64_t n, int64_t nnz, const void* row_offsets, int of
       if (e != hipSuccess) rc = hip_fail(e, "upload");
     }
     if (rc == BFS_OK && !(flags & BFS_TRUSTED)) rc = csr_validate(g, s);
-    if (rc == BFS_OK) {
+    const bool upper = (flags & BFS_UPPER) != 0;
+    if (rc == BFS_OK && upper) {
+      // the symmetric closure is searched; the stored half is traversed in
+      // its own ids (no degree-ordered copy, which would double it)
+      c.upper = 1;
+      if (!(flags & BFS_TRUSTED)) {
+        int ok = 0;
+        rc = csr_check_upper(g, s, &ok);
+        if (rc == BFS_OK && !ok)
+          rc = fail(BFS_ERR_FORMAT,
+                    "BFS_UPPER: every adjacency v of row u must satisfy v > u, rows ascending");
+      }
+    } else if (rc == BFS_OK) {
       if (flags & BFS_SYMMETRIC) c.symmetric = 1;
       else if (!(flags & BFS_TRUSTED)) rc = csr_check_symmetric(g, s, &c.symmetric);
     }
     // degree-ordered copy for the level kernels (large graphs)
-    if (rc == BFS_OK && !(flags & BFS_NO_RELABEL) && n >= ((int64_t)1 << 20) && nnz > 0) {
+    if (rc == BFS_OK && !upper && !(flags & BFS_NO_RELABEL) && n >= ((int64_t)1 << 20) &&
+        nnz > 0) {
       std::vector<int64_t> hoff;
       const int64_t* ho = nullptr;
       if (offset_bytes == 8 && !dev) {
@@ -146,7 +168,7 @@ int bfs_graph_create_csr(int64_t n, int64_t nnz, const void* row_offsets, int of
     }
     if (rc == BFS_OK) rc = csr_alloc_workspace(g);
     if (rc == BFS_OK) {
-      e = hipHostMalloc(&g->h_ctr, sizeof(unsigned long long), hipHostMallocDefault);
+      e = hipHostMalloc(&g->h_ctr, 16 * sizeof(unsigned long long), hipHostMallocDefault);
       if (e != hipSuccess) rc = hip_fail(e, "pinned counter");
     }
     if (rc != BFS_OK) return bail(rc);
@@ -238,10 +260,12 @@ int bfs_graph_set_options(bfs_graph_t* g, const bfs_options_t* opt) {
     return fail(BFS_ERR_ARG, "cold_probe must be 1, 2 or 3");
   if (opt->spmspv_sort_max < -1) return fail(BFS_ERR_ARG, "spmspv_sort_max must be >= -1");
   if (opt->pull_alpha < -1) return fail(BFS_ERR_ARG, "pull_alpha must be >= -1");
+  if (opt->small_frontier < -1) return fail(BFS_ERR_ARG, "small_frontier must be >= -1");
   // every field checked: apply
   if (opt->cold_probe) g->opt.cold_probe = opt->cold_probe;
   if (opt->spmspv_sort_max) g->opt.spmspv_sort_max = opt->spmspv_sort_max;
   if (opt->pull_alpha) g->opt.pull_alpha = opt->pull_alpha;
+  if (opt->small_frontier) g->opt.small_frontier = opt->small_frontier < 0 ? -1 : opt->small_frontier;
   if (opt->claim) g->opt.claim = opt->claim;
   if (opt->claim_threshold) g->opt.claim_threshold = opt->claim_threshold;
   if (opt->claim_min_frontier) g->opt.claim_min_frontier = opt->claim_min_frontier;

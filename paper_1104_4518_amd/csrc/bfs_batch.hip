@@ -1,6 +1,6 @@
 // bfs_run_batch: many independent BFS queries in one launch of the
-// multi-query kernel, and bfs_tune: picks expand-kernel launch shapes for a
-// graph by timing them.
+// multi-query kernel, and bfs_tune: picks launch shapes and level thresholds
+// for a graph (or the SpMSpV branch switch for a DCSC share) by timing them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,7 +33,19 @@ struct BatchPool {
   int32_t* d_counter = nullptr;
   MQuery* h_qs = nullptr;
   int32_t* h_order = nullptr;
+  hipStream_t lane = nullptr;   // queries run through the level kernels
+  int lane_device = -1;
 };
+
+// Queries on graphs this large with an average degree of 8 or more (a few
+// levels) run one at a time through the whole-GPU level kernels, beside the
+// multi-query launch: one workgroup would take hundreds of times longer on
+// them (R-MAT scale 22: ~0.4 ms across the GPU, ~400 ms in one workgroup).
+constexpr int64_t kBatchLaneNnz = (int64_t)1 << 23;
+
+bool batch_lane(const bfs_graph* g) {
+  return g->csr.nnz >= kBatchLaneNnz && g->csr.nnz >= 8 * g->csr.n;
+}
 
 BatchPool& pool() {
   static BatchPool p;
@@ -87,9 +99,15 @@ double query_cost(const bfs_graph* g) {
   return edges * 0.5 + depth * 4000.0;
 }
 
-// Launch shapes and the mark-level frontier floor of a CSR graph: BFS from
-// its three largest-degree vertices (among the first 2^22) under each
-// setting, the fastest kept.
+// Launch shapes and level floors of a CSR graph, chosen by timing BFS from
+// eight seeded roots of positive degree. Coordinate descent from the
+// defaults: each knob in turn tries its values with the others fixed, each
+// setting timed as the median of three passes over the roots, and a value
+// replaces the current one only when it is faster by more than kTuneMargin,
+// so settings within timing noise of each other keep the earlier one and
+// repeated tuning gives the same choice. Two sweeps over the knobs.
+constexpr double kTuneMargin = 0.03;
+
 int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   const int64_t n = g->csr.n;
   int32_t *parent = nullptr, *level = nullptr;
@@ -114,61 +132,70 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   std::lock_guard<std::mutex> run_lk(g->run_mu);
   const bfs_options_t saved = g->opt;
   const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  double best = 1e30;
-  int best_grid = cus * 4, best_batch = 4, best_minf = 4096, best_alpha = 14, best_ct = 0;
-  int rc = BFS_OK;
   // mark-level edge floor: the default (n / 64), or a sixteenth of the
   // adjacencies (graphs without hubs, where a push level's resolve scans far
   // for a small frontier's vertices)
-  const int64_t ct16 = std::min<int64_t>(g->csr.nnz / 16, INT32_MAX);
-  for (int per_cu : {2, 4}) {
-    for (int batch : {4, 8}) {
-      for (int minf : {1024, 4096, 16384})
-      for (int alpha : {4, 14, 40})
-      for (int ct : {0, (int)ct16}) {
-        g->opt.grid_blocks = cus * per_cu;
-        g->opt.batch_levels = batch;
-        g->opt.claim_min_frontier = minf;
-        g->opt.pull_alpha = alpha;
-        g->opt.claim_threshold = ct;
-        rc = csr_run(g, cand[0], parent, level, nullptr, true);   // warm
+  const int ct16 = (int)std::min<int64_t>(g->csr.nnz / 16, INT32_MAX);
+  struct Knob {
+    int32_t bfs_options_t::*field;
+    std::vector<int32_t> values;   // values[0] is the default
+  };
+  const std::vector<Knob> knobs = {
+      {&bfs_options_t::grid_blocks, {cus * 2, cus * 4}},
+      {&bfs_options_t::batch_levels, {4, 8}},
+      {&bfs_options_t::claim_min_frontier, {4096, 1024, 16384}},
+      {&bfs_options_t::pull_alpha, {14, 4, 40}},
+      {&bfs_options_t::claim_threshold, {0, ct16}},
+      {&bfs_options_t::small_frontier, {8192, 1024, -1}},
+  };
+  bfs_options_t cur = saved;
+  for (const Knob& kb : knobs) cur.*(kb.field) = kb.values[0];
+  int rc = BFS_OK;
+  auto measure = [&](const bfs_options_t& o, double* out) -> int {
+    g->opt = o;
+    int r = csr_run(g, cand[0], parent, level, nullptr, true);   // warm
+    if (r != BFS_OK) return r;
+    double t[3];
+    for (int pass = 0; pass < 3; ++pass) {
+      const auto t0 = std::chrono::steady_clock::now();
+      for (int32_t root : cand) {
+        r = csr_run(g, root, parent, level, nullptr, true);
+        if (r != BFS_OK) return r;
+      }
+      t[pass] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    std::sort(t, t + 3);
+    *out = t[1];
+    return BFS_OK;
+  };
+  double best = 0.0;
+  rc = measure(cur, &best);
+  for (int sweep = 0; sweep < 2 && rc == BFS_OK; ++sweep) {
+    for (const Knob& kb : knobs) {
+      for (int32_t v : kb.values) {
+        if (cur.*(kb.field) == v) continue;
+        bfs_options_t o = cur;
+        o.*(kb.field) = v;
+        double t = 0.0;
+        rc = measure(o, &t);
         if (rc != BFS_OK) break;
-        // the better of two passes over the roots (timing noise)
-        double dt = 1e30;
-        for (int pass = 0; pass < 2 && rc == BFS_OK; ++pass) {
-          const auto t0 = std::chrono::steady_clock::now();
-          for (int32_t r : cand) {
-            rc = csr_run(g, r, parent, level, nullptr, true);
-            if (rc != BFS_OK) break;
-          }
-          dt = std::min(dt, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0)
-                                .count());
-        }
-        if (rc == BFS_OK && dt < best) {
-          best = dt;
-          best_grid = g->opt.grid_blocks;
-          best_batch = batch;
-          best_minf = minf;
-          best_alpha = alpha;
-          best_ct = ct;
+        if (t < best * (1.0 - kTuneMargin)) {
+          best = t;
+          cur = o;
         }
       }
       if (rc != BFS_OK) break;
     }
-    if (rc != BFS_OK) break;
   }
   (void)hipFree(parent);
   (void)hipFree(level);
   g->opt = saved;
   if (rc != BFS_OK) return rc;
-  g->opt.grid_blocks = best_grid;
-  g->opt.batch_levels = best_batch;
-  g->opt.claim_min_frontier = best_minf;
-  g->opt.pull_alpha = best_alpha;
-  g->opt.claim_threshold = best_ct;
+  for (const Knob& kb : knobs) g->opt.*(kb.field) = cur.*(kb.field);
   std::ostringstream o;
-  o << "grid=" << best_grid << " batch=" << best_batch << " min_frontier=" << best_minf
-    << " pull_alpha=" << best_alpha << " claim_threshold=" << best_ct;
+  o << "grid=" << cur.grid_blocks << " batch=" << cur.batch_levels
+    << " min_frontier=" << cur.claim_min_frontier << " pull_alpha=" << cur.pull_alpha
+    << " claim_threshold=" << cur.claim_threshold << " small_frontier=" << cur.small_frontier;
   *result = o.str();
   return BFS_OK;
 }
@@ -216,7 +243,7 @@ int tune_dcsc(bfs_graph* g, std::string* result) {
       t[path] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     if (rc != BFS_OK) break;
-    if (t[1] < t[0]) chosen = k;
+    if (t[1] < t[0] * (1.0 - kTuneMargin)) chosen = k;
   }
   (void)hipFree(f);
   (void)hipFree(oi);
@@ -242,10 +269,11 @@ int bfs_run_batch(int32_t count, bfs_graph_t* const* graphs, const int32_t* root
     if (count == 0) return BFS_OK;
     if (!graphs || !roots || !parents) return fail(BFS_ERR_ARG, "NULL argument array");
     std::unordered_set<const void*> outs;
-    int64_t nmax = 1;
     for (int32_t i = 0; i < count; ++i) {
       const bfs_graph* g = graphs[i];
       if (!g || g->kind != kCsr) return fail(BFS_ERR_ARG, "batch query needs a CSR graph");
+      if (g->csr.upper)
+        return fail(BFS_ERR_UNSUPPORTED, "batch queries need full CSR graphs (not BFS_UPPER)");
       if (roots[i] < 0 || (int64_t)roots[i] >= g->csr.n)
         return fail(BFS_ERR_ARG, "root out of range in batch");
       if (!parents[i] || !device_ptr(parents[i]))
@@ -256,60 +284,89 @@ int bfs_run_batch(int32_t count, bfs_graph_t* const* graphs, const int32_t* root
         if (!outs.insert(levels[i]).second)
           return fail(BFS_ERR_ARG, "batch outputs must not alias");
       }
-      nmax = std::max<int64_t>(nmax, g->csr.n);
     }
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     BatchPool& p = pool();
     std::lock_guard<std::mutex> lk(p.mu);
     int dev = 0;
     (void)hipGetDevice(&dev);
-
-    // workgroups: co-resident capacity, bounded by the queries and by a
-    // quarter of free memory for their workspaces
-    const int64_t ws_one = multi_ws_bytes(nmax);
-    size_t free_b = 0, total_b = 0;
-    (void)hipMemGetInfo(&free_b, &total_b);
-    int64_t grid = std::min<int64_t>(count, multi_grid(dev));
-    const int64_t mem_cap = std::max<int64_t>(1, (int64_t)(free_b + p.ws_bytes) / 4 / ws_one);
-    grid = std::max<int64_t>(1, std::min(grid, mem_cap));
-    int rc = grow(p, count, grid * ws_one);
-    if (rc != BFS_OK) return rc;
-
-    std::vector<std::pair<double, int32_t>> cost((size_t)count);
+    std::vector<int32_t> multi, lane;
+    int64_t nmax = 1;
     for (int32_t i = 0; i < count; ++i) {
-      const bfs_graph* g = graphs[i];
-      MQuery& q = p.h_qs[i];
-      std::memset(&q, 0, sizeof(q));
-      q.off = g->csr.off;
-      q.col = g->csr.col;
-      q.parent = parents[i];
-      q.level = levels ? levels[i] : nullptr;
-      q.n = (int32_t)g->csr.n;
-      q.root = roots[i];
-      q.status = kQueryPending;
-      cost[(size_t)i] = {query_cost(g), i};
+      if (batch_lane(graphs[i])) {
+        lane.push_back(i);
+      } else {
+        multi.push_back(i);
+        nmax = std::max<int64_t>(nmax, graphs[i]->csr.n);
+      }
     }
-    std::stable_sort(cost.begin(), cost.end(),
-                     [](const auto& a, const auto& b) { return a.first > b.first; });
-    for (int32_t i = 0; i < count; ++i) p.h_order[i] = cost[(size_t)i].second;
-
-    BFS_HIP(hipMemcpyAsync(p.d_qs, p.h_qs, (size_t)count * sizeof(MQuery),
-                           hipMemcpyHostToDevice, s));
-    BFS_HIP(hipMemcpyAsync(p.d_order, p.h_order, (size_t)count * 4, hipMemcpyHostToDevice, s));
-    rc = multi_reset_counter(p.d_counter, s);
-    if (rc != BFS_OK) return rc;
-    rc = multi_launch(p.d_qs, p.d_order, count, p.d_counter, (int)grid, true, 0ull, p.ws, ws_one,
-                      multi_q_bytes(nmax), s);
-    if (rc != BFS_OK) return rc;
-    BFS_HIP(hipMemcpyAsync(p.h_qs, p.d_qs, (size_t)count * sizeof(MQuery),
-                           hipMemcpyDeviceToHost, s));
-    BFS_HIP(hipStreamSynchronize(s));
-    for (int32_t i = 0; i < count; ++i) {
-      const MQuery& q = p.h_qs[i];
-      if (q.status != kQueryDone) return fail(BFS_ERR_DEVICE, "batch query did not complete");
-      bfs_graph* g = graphs[i];
-      g->hint_depth = std::max(g->hint_depth, q.depth);
-      g->hint_edges = std::max<int64_t>(g->hint_edges, (int64_t)q.edges);
+    const int32_t nm = (int32_t)multi.size();
+    int rc = BFS_OK;
+    if (nm > 0) {
+      // workgroups: co-resident capacity, bounded by the queries and by a
+      // quarter of free memory for their workspaces
+      const int64_t ws_one = multi_ws_bytes(nmax);
+      size_t free_b = 0, total_b = 0;
+      (void)hipMemGetInfo(&free_b, &total_b);
+      int64_t grid = std::min<int64_t>(nm, multi_grid(dev));
+      const int64_t mem_cap = std::max<int64_t>(1, (int64_t)(free_b + p.ws_bytes) / 4 / ws_one);
+      grid = std::max<int64_t>(1, std::min(grid, mem_cap));
+      rc = grow(p, nm, grid * ws_one);
+      if (rc != BFS_OK) return rc;
+      std::vector<std::pair<double, int32_t>> cost((size_t)nm);
+      for (int32_t j = 0; j < nm; ++j) {
+        const int32_t i = multi[(size_t)j];
+        const bfs_graph* g = graphs[i];
+        MQuery& q = p.h_qs[j];
+        std::memset(&q, 0, sizeof(q));
+        q.off = g->csr.off;
+        q.col = g->csr.col;
+        q.parent = parents[i];
+        q.level = levels ? levels[i] : nullptr;
+        q.n = (int32_t)g->csr.n;
+        q.root = roots[i];
+        q.status = kQueryPending;
+        cost[(size_t)j] = {query_cost(g), j};
+      }
+      std::stable_sort(cost.begin(), cost.end(),
+                       [](const auto& a, const auto& b) { return a.first > b.first; });
+      for (int32_t j = 0; j < nm; ++j) p.h_order[j] = cost[(size_t)j].second;
+      BFS_HIP(hipMemcpyAsync(p.d_qs, p.h_qs, (size_t)nm * sizeof(MQuery),
+                             hipMemcpyHostToDevice, s));
+      BFS_HIP(hipMemcpyAsync(p.d_order, p.h_order, (size_t)nm * 4, hipMemcpyHostToDevice, s));
+      rc = multi_reset_counter(p.d_counter, s);
+      if (rc != BFS_OK) return rc;
+      rc = multi_launch(p.d_qs, p.d_order, nm, p.d_counter, (int)grid, true, 0ull, p.ws, ws_one,
+                        multi_q_bytes(nmax), s);
+      if (rc != BFS_OK) return rc;
+      BFS_HIP(hipMemcpyAsync(p.h_qs, p.d_qs, (size_t)nm * sizeof(MQuery),
+                             hipMemcpyDeviceToHost, s));
+    }
+    // the large queries, one at a time on the lane stream, while the
+    // multi-query launch runs
+    if (!lane.empty()) {
+      if (!p.lane || p.lane_device != dev) {
+        if (p.lane) (void)hipStreamDestroy(p.lane);
+        p.lane = nullptr;
+        BFS_HIP(hipStreamCreateWithFlags(&p.lane, hipStreamNonBlocking));
+        p.lane_device = dev;
+      }
+      for (int32_t i : lane) {
+        bfs_graph* g = graphs[i];
+        std::lock_guard<std::mutex> gl(g->run_mu);
+        rc = csr_run(g, roots[i], parents[i], levels ? levels[i] : nullptr, p.lane, true);
+        if (rc != BFS_OK) return rc;
+      }
+    }
+    if (nm > 0) {
+      BFS_HIP(wait_stream(s));
+      for (int32_t j = 0; j < nm; ++j) {
+        const MQuery& q = p.h_qs[j];
+        if (q.status != kQueryDone) return fail(BFS_ERR_DEVICE, "batch query did not complete");
+        bfs_graph* g = graphs[multi[(size_t)j]];
+        g->hint_depth = std::max(g->hint_depth, q.depth);
+        g->hint_edges = std::max<int64_t>(g->hint_edges, (int64_t)q.edges);
+      }
     }
     return BFS_OK;
   } catch (...) {
@@ -337,16 +394,20 @@ int bfs_tune(bfs_graph_t* g, const char* cache_path) {
         const size_t bar = line.find(" | ");
         if (bar == std::string::npos || line.substr(0, bar) != key.str()) continue;
         const char* rest = line.c_str() + bar + 3;
-        int grid = 0, batch = 0, minf = 0, alpha = 0, ct = -1, sort_max = 0;
+        int grid = 0, batch = 0, minf = 0, alpha = 0, ct = -1, small = 0, sort_max = 0;
         if (g->kind == kCsr &&
-            std::sscanf(rest, "grid=%d batch=%d min_frontier=%d pull_alpha=%d claim_threshold=%d",
-                        &grid, &batch, &minf, &alpha, &ct) == 5 &&
-            grid > 0 && batch > 0 && minf > 0 && (alpha > 0 || alpha == -1) && ct >= 0) {
+            std::sscanf(rest,
+                        "grid=%d batch=%d min_frontier=%d pull_alpha=%d claim_threshold=%d "
+                        "small_frontier=%d",
+                        &grid, &batch, &minf, &alpha, &ct, &small) == 6 &&
+            grid > 0 && batch > 0 && minf > 0 && (alpha > 0 || alpha == -1) && ct >= 0 &&
+            (small > 0 || small == -1)) {
           g->opt.grid_blocks = grid;
           g->opt.batch_levels = batch;
           g->opt.claim_min_frontier = minf;
           g->opt.pull_alpha = alpha;
           g->opt.claim_threshold = ct;
+          g->opt.small_frontier = small;
           return BFS_OK;
         }
         if (g->kind == kDcsc && std::sscanf(rest, "sort_max=%d", &sort_max) == 1 &&

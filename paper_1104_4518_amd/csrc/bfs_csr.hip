@@ -72,7 +72,7 @@ __global__ void k_init(int64_t n_active, unsigned long long* __restrict__ rpl,
                        uint32_t* __restrict__ vis, int64_t nwords, uint4* __restrict__ mark,
                        const int64_t* __restrict__ off, int32_t root,
                        const int32_t* __restrict__ rank, Queues q, int32_t* jstart,
-                       LevelState* st, int cbits) {
+                       LevelState* st, int cbits, uint32_t* __restrict__ fbits) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int32_t r = rank ? rank[root] : root;
@@ -81,6 +81,10 @@ __global__ void k_init(int64_t n_active, unsigned long long* __restrict__ rpl,
   for (int64_t w = i; w < nwords; w += stride) {
     const bool rw = w == (r >> 5);
     vis[w] = rw ? 1u << (r & 31) : 0u;
+    if (fbits) {   // upper-triangle graphs: frontier 0 = {root}, the other parity empty
+      fbits[w] = rw ? 1u << (r & 31) : 0u;
+      fbits[nwords + w] = 0u;
+    }
     if (mark) {
       uint32_t x[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
       if (rw) x[(r & 31) >> 2] = (uint32_t)level_tag(0) << (8 * (r & 3));
@@ -107,7 +111,11 @@ __global__ void k_init(int64_t n_active, unsigned long long* __restrict__ rpl,
   st->edges = 0ull;
   st->reached = 1ull;
   st->frontier_total = 0ull;
-  st->zcnt[0] = st->zcnt[1] = st->zcnt[2] = 0u;
+  // an upper-triangle graph's root without a stored row is still a frontier
+  // vertex (its smaller neighbours find it in their rows): it counts as a
+  // frontier vertex without adjacencies (its bits are set above)
+  st->zcnt[0] = (d == 0 && fbits) ? 1u : 0u;
+  st->zcnt[1] = st->zcnt[2] = 0u;
   st->error = 0;
   st->mark_levels = 0;
   st->pull = 0;
@@ -118,6 +126,8 @@ __global__ void k_init(int64_t n_active, unsigned long long* __restrict__ rpl,
   st->qskip = 0;
   st->kind_cur = 0;
   st->kind_prev = 0;
+  st->groups = 0;
+  st->small_levels = 0;
 }
 
 // Block-wide exclusive scan of (count, degree sum) pairs; returns the
@@ -150,13 +160,6 @@ __device__ __forceinline__ void block_scan2(long long c, long long d, long long*
   }
   ex_c = bc + ic - c;
   ex_d = bd + id - d;
-}
-
-// Map the edge tiles of the next level that start inside [e, e + d) to
-// queue entry j.
-__device__ __forceinline__ void map_tiles(int32_t* __restrict__ jstart, long long e, long long d,
-                                          int32_t j) {
-  for (long long w = (e + kTileJ - 1) / kTileJ; w * kTileJ < e + d; ++w) jstart[w] = j;
 }
 
 // Bitmap of the vertices at level k-1 (mark byte = its tag), built by the
@@ -194,7 +197,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     const uint32_t* __restrict__ vis, unsigned long long* __restrict__ rpl,
     uint8_t* __restrict__ mark, Queues q, int32_t* __restrict__ jstart_base, int64_t njs,
     int32_t* __restrict__ zq, LevelState* st, int cbits, MarkPolicy mp,
-    const int32_t* __restrict__ inv, int64_t nwords, uint32_t* __restrict__ prev_bits) {
+    const int32_t* __restrict__ inv, int64_t nwords, uint32_t* __restrict__ prev_bits,
+    uint32_t* __restrict__ fbits, int opens_group) {
   constexpr int WAVES = BLOCK / 64;
   // the tile's rows: edge prefix, adjacency start, caller's id
   __shared__ __align__(16) long long s_qe[kTileJ + 1];
@@ -211,13 +215,26 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   const unsigned long long cin = st->ctr[kin % 3];
   const int64_t F = (int64_t)(cin & cmask);
   const int64_t T = (int64_t)(cin >> cbits);
+  // an upper-triangle graph's frontier may hold only vertices without
+  // stored rows (counted in zcnt): the level still runs its reverse search
+  const bool live = F > 0 || (fbits && st->zcnt[kin % 3] > 0);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // the launch group of this level's kernels: opened here, or by the
+    // device level loop launched just before
+    const int grp = opens_group ? st->groups++ : st->groups - 1;
+    if (grp >= 0 && grp < kLevelHist) {
+      if (opens_group) {
+        st->grp_first[grp] = 1;
+        st->grp_last[grp] = 0;
+      }
+      st->grp_level[grp] = live ? k : 0;
+    }
     st->ctr[(k + 1) % 3] = 0ull;   // output counters of level k + 1
     st->zcnt[(k + 1) % 3] = 0u;
     st->k_fold = k;
     int pull = 0;
+    if (live) st->levels = k;
     if (F > 0) {
-      st->levels = k;
       st->edges += (unsigned long long)T;
       st->frontier_total += (unsigned long long)F;
       if (mark_level(cin, cbits, mp)) {
@@ -240,6 +257,16 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
       st->hist_pc[k] = 0ull;
       st->hist_pe[k] = 0ull;
     }
+  }
+  if (!live) return;
+  if (fbits) {
+    // upper-triangle graphs: the bitmap of parity k & 1 held frontier k - 2
+    // and receives level k's vertices in finish(k); the reverse search of
+    // this level reads the other one (frontier k - 1)
+    uint32_t* __restrict__ fb = fbits + (int64_t)(k & 1) * nwords;
+    for (int64_t w = blockIdx.x * (int64_t)BLOCK + threadIdx.x; w < nwords;
+         w += (int64_t)gridDim.x * BLOCK)
+      fb[w] = 0u;
   }
   if (F == 0) return;
   const bool cmark = claim_mark_level(cin, cbits, mp);
@@ -379,13 +406,16 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
           s_od[p] = deg;
         }
       }
-      // reached but nothing to expand (out-degree 0): finish(k) marks it visited
-      const unsigned long long mz = wave_ballot(own && deg == 0);
+      // reached but nothing to expand (out-degree 0): finish(k) marks it
+      // visited (on an upper-triangle graph it stays a frontier vertex, found
+      // by its smaller neighbours' reverse search)
+      const bool zero = own && deg == 0;
+      const unsigned long long mz = wave_ballot(zero);
       if (mz) {
         unsigned int base = 0;
         if (lane == 0) base = atomicAdd(&st->zcnt[k % 3], (unsigned int)__popcll(mz));
         base = __shfl(base, 0, 64);
-        if (own && deg == 0) zq[base + lanes_below(mz)] = v;
+        if (zero) zq[base + lanes_below(mz)] = v;
       }
     }
     __syncthreads();
@@ -449,7 +479,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
     const int64_t* __restrict__ off, uint32_t* __restrict__ vis, uint8_t* __restrict__ mark,
     Queues q, int32_t* __restrict__ jstart_base, int64_t njs, const int32_t* __restrict__ zq,
     LevelState* st, int cbits, int64_t n, int64_t nwords, MarkPolicy mp, int hw,
-    const uint32_t* __restrict__ hot_new, int nslices) {
+    const uint32_t* __restrict__ hot_new, int nslices, uint32_t* __restrict__ fbits) {
   __shared__ long long s_wc[BLOCK / 64], s_wd[BLOCK / 64];
   __shared__ unsigned long long s_base;
   __shared__ int s_exw[BLOCK / 64][64];
@@ -458,7 +488,9 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
   const unsigned long long cmask = (1ull << cbits) - 1;
   const unsigned long long cin = st->ctr[(k - 1) % 3];
   if (blockIdx.x == 0 && threadIdx.x == 0) st->k_expand = k + 1;
-  if ((cin & cmask) == 0) return;   // the level did not run
+  // the level did not run (an upper-triangle graph's frontier may hold only
+  // vertices without stored rows)
+  if ((cin & cmask) == 0 && !(fbits && st->zcnt[(k - 1) % 3] > 0)) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int tid = threadIdx.x;
 
@@ -495,11 +527,13 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
       for (int64_t j = blockIdx.x * (int64_t)blockDim.x + tid; j < F; j += stride) {
         const int32_t v = qv[j];
         atomicOr(&vis[v >> 5], 1u << (v & 31));
+        if (fbits) atomicOr(&fbits[(int64_t)(k & 1) * nwords + (v >> 5)], 1u << (v & 31));
       }
     }
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + tid; j < Z; j += stride) {
       const int32_t v = zq[j];
       atomicOr(&vis[v >> 5], 1u << (v & 31));
+      if (fbits) atomicOr(&fbits[(int64_t)(k & 1) * nwords + (v >> 5)], 1u << (v & 31));
     }
     return;
   }
@@ -690,6 +724,214 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
 }
 
 
+// Upper-triangle graphs (each undirected edge stored once, in the row of its
+// smaller endpoint, rows ascending): the first vertex of the frontier bitmap
+// fb in row [o, end) of v, searched in ascending order, p = it and at = its
+// position (p = -1, at = end when there is none). Each thread scans its row
+// four entries at a time up to kSerialScan; the wave finishes longer rows
+// together, 64 per step, so every lane of the wave must make the call.
+__device__ __forceinline__ void upper_first_hit(const int32_t* __restrict__ col,
+                                                const uint32_t* __restrict__ fb, int lane,
+                                                int32_t v, int64_t o, int64_t end, int32_t& p,
+                                                int64_t& at) {
+  p = -1;
+  at = end;
+  bool pending = false;
+  if (v >= 0) {
+    const int64_t lim = min(end, o + (int64_t)kSerialScan);
+    for (int64_t e = o; e < lim && p < 0; e += 4) {
+      int32_t u4[4];
+      uint32_t b4[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) u4[i] = e + i < lim ? col[e + i] : -1;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b4[i] = u4[i] >= 0 ? fb[u4[i] >> 5] : 0u;
+#pragma unroll
+      for (int i = 3; i >= 0; --i)
+        if (u4[i] >= 0 && ((b4[i] >> (u4[i] & 31)) & 1u)) {
+          p = u4[i];
+          at = e + i;
+        }
+    }
+    pending = p < 0 && end - o > kSerialScan;
+  }
+  for (;;) {
+    const unsigned long long pend = wave_ballot(pending);
+    if (!pend) break;
+    const int leader = __ffsll((long long)pend) - 1;
+    const int64_t lo = shfl_ll(o + kSerialScan, leader);
+    const int64_t hi = shfl_ll(end, leader);
+    int32_t found = -1;
+    int64_t fat = hi;
+    for (int64_t e0 = lo; e0 < hi; e0 += 64) {
+      const int64_t e = e0 + lane;
+      int32_t uu = 0;
+      bool hit = false;
+      if (e < hi) {
+        uu = col[e];
+        hit = (fb[uu >> 5] >> (uu & 31)) & 1u;
+      }
+      const unsigned long long hb = wave_ballot(hit);
+      if (hb) {
+        const int src = __ffsll((long long)hb) - 1;
+        found = __shfl(uu, src, 64);
+        fat = e0 + src;
+        break;
+      }
+    }
+    if (lane == leader) {
+      p = found;
+      at = fat;
+      pending = false;
+    }
+  }
+}
+
+// reverse(k), upper-triangle graphs: the part of the level's product that
+// the push cannot reach. Frontier vertex u pushes (k_expand's claim path)
+// only to its larger neighbours, the ones stored in its own row; a vertex w
+// adjacent to the frontier only through larger neighbours holds those edges
+// in its own row. So every vertex unvisited before level k and not claimed
+// by the push scans its row in ascending order for the first vertex of
+// frontier k-1 (its bit in the frontier bitmap): that vertex is its parent,
+// the minimum frontier neighbour, since it has none smaller (the push would
+// have claimed it). Found vertices join the next frontier like claimed ones
+// (one packed atomic per wave and round reserves their queue slots and
+// edge range). Each wave takes 64 words of the visited bitmap (2048
+// vertices) and lists their unvisited vertices in LDS.
+constexpr int kRevBlock = 256;
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_reverse(
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+    const uint32_t* __restrict__ vis, unsigned long long* __restrict__ rpl,
+    const uint32_t* __restrict__ fbits, Queues q, int32_t* __restrict__ jstart_base, int64_t njs,
+    int32_t* __restrict__ zq, LevelState* st, int cbits, int64_t n, int64_t nwords) {
+  constexpr int WAVES = BLOCK / 64;
+  __shared__ int s_exw[WAVES][64];
+  __shared__ uint32_t s_m[WAVES][64];
+  __shared__ unsigned long long s_red[3][WAVES];
+  const int k = st->k_fold;
+  const unsigned long long cmask = (1ull << cbits) - 1;
+  const unsigned long long cin = st->ctr[(k - 1) % 3];
+  if ((cin & cmask) == 0 && st->zcnt[(k - 1) % 3] == 0) return;   // empty frontier
+  const uint32_t* __restrict__ fb = fbits + (int64_t)((k - 1) & 1) * nwords;
+  int32_t* __restrict__ jstart = jstart_base + (int64_t)(k & 1) * njs;
+  int32_t* __restrict__ qv_out = q.qv[k & 1];
+  int64_t* __restrict__ qo_out = q.qo[k & 1];
+  int64_t* __restrict__ qe_out = q.qe[k & 1];
+  unsigned long long* ctr_out = &st->ctr[k % 3];
+  const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+  const int64_t nchunks = (nwords + 63) >> 6;
+  const int64_t nwaves = (int64_t)gridDim.x * WAVES;
+  unsigned long long my_found = 0, my_cand = 0, my_edges = 0;
+  for (int64_t c = (int64_t)blockIdx.x * WAVES + wid; c < nchunks; c += nwaves) {
+    const int64_t w = (c << 6) + lane;
+    uint32_t m = 0u;
+    if (w < nwords) {
+      m = ~vis[w];
+      const int64_t left = n - (w << 5);
+      if (left < 32) m &= (1u << left) - 1u;
+    }
+    const int cnt = __popc(m);
+    const int incl = (int)wave_incl_scan((long long)cnt);
+    const int total = __shfl(incl, 63, 64);
+    s_exw[wid][lane] = incl - cnt;
+    s_m[wid][lane] = m;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int r = 0; r < total; r += 64) {
+      const int i = r + lane;
+      int32_t v = -1;
+      if (i < total) {
+        int lo = 0;   // last lane whose list starts at or before i
+#pragma unroll
+        for (int step = 32; step; step >>= 1)
+          if (lo + step <= 63 && s_exw[wid][lo + step] <= i) lo += step;
+        v = (int32_t)((((c << 6) + lo) << 5) + select_bit(s_m[wid][lo], i - s_exw[wid][lo]));
+      }
+      int64_t o = 0, e = 0;
+      if (v >= 0) {
+        if (rpl[v] != ~0ull) {
+          v = -1;   // claimed by this level's push: its parent is smaller
+        } else {
+          o = off[v];
+          e = off[v + 1];
+        }
+      }
+      int32_t p;
+      int64_t at;
+      upper_first_hit(col, fb, lane, v, o, e, p, at);
+      const bool found = p >= 0;
+      if (v >= 0) {
+        ++my_cand;
+        my_edges += (unsigned long long)(found ? at - o + 1 : e - o);
+      }
+      if (found) rpl[v] = ((unsigned long long)k << 32) | (uint32_t)p;
+      const int64_t d = found ? e - o : 0;
+      const bool enq = found && d > 0;
+      const unsigned long long mq = wave_ballot(enq);
+      if (mq) {
+        const long long dincl = wave_incl_scan(enq ? d : 0);
+        const long long dsum = shfl_ll(dincl, 63);
+        unsigned long long base = 0;
+        if (lane == 0)
+          base = atomicAdd(ctr_out, ((unsigned long long)dsum << cbits) |
+                                        (unsigned long long)__popcll(mq));
+        base = (unsigned long long)shfl_ll((long long)base, 0);
+        if (enq) {
+          const int64_t slot = (int64_t)(base & cmask) + lanes_below(mq);
+          const long long ebeg = (long long)(base >> cbits) + dincl - d;
+          qv_out[slot] = v;
+          qo_out[slot] = o;
+          qe_out[slot] = ebeg;
+          map_tiles(jstart, ebeg, d, (int32_t)slot);
+        }
+      }
+      // found, without a row of its own: a frontier vertex all the same
+      // (finish(k) sets its bits)
+      const unsigned long long mz = wave_ballot(found && d == 0);
+      if (mz) {
+        unsigned int base = 0;
+        if (lane == 0) base = atomicAdd(&st->zcnt[k % 3], (unsigned int)__popcll(mz));
+        base = __shfl(base, 0, 64);
+        if (found && d == 0) zq[base + lanes_below(mz)] = v;
+      }
+      my_found += found;
+    }
+    __builtin_amdgcn_wave_barrier();   // the wave's lists are rewritten by its next chunk
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    my_found += __shfl_xor(my_found, d, 64);
+    my_cand += __shfl_xor(my_cand, d, 64);
+    my_edges += __shfl_xor(my_edges, d, 64);
+  }
+  if (lane == 0) {
+    s_red[0][wid] = my_found;
+    s_red[1][wid] = my_cand;
+    s_red[2][wid] = my_edges;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long f = 0, a = 0, b = 0;
+    for (int x = 0; x < WAVES; ++x) {
+      f += s_red[0][x];
+      a += s_red[1][x];
+      b += s_red[2][x];
+    }
+    if (f) {
+      atomicAdd(&st->reached, f);
+      atomicMax(&st->depth, k);
+    }
+    if (k < kLevelHist && a) {
+      atomicAdd(&st->hist_pc[k], a);
+      atomicAdd(&st->hist_pe[k], b);
+    }
+  }
+}
+
 __global__ void k_build_head(int64_t n, const int64_t* __restrict__ off,
                              const int32_t* __restrict__ col, int4* __restrict__ head) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -813,6 +1055,24 @@ __global__ void k_check_symmetric(int64_t n, int64_t nnz, const int64_t* __restr
   }
 }
 
+// Upper triangle: every adjacency v of row u has v > u and follows a
+// smaller one in its row. Sets *bad on a violation. Runs only on validated
+// CSR arrays.
+__global__ void k_check_upper(int64_t n, int64_t nnz, const int64_t* __restrict__ off,
+                              const int32_t* __restrict__ col, int32_t* bad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += stride) {
+    int64_t prev = u;
+    for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+      if ((int64_t)col[e] <= prev) {
+        atomicOr(bad, 1);
+        break;
+      }
+      prev = col[e];
+    }
+  }
+}
+
 // Degree-ordered copy: row v' of the copy is row inv[v'] of the original with
 // every adjacency mapped through rank (order within the row unchanged, so it
 // stays ascending in original ids). One wave per row.
@@ -863,6 +1123,10 @@ int csr_alloc_workspace(bfs_graph* g) {
   BFS_HIP(hipMalloc(&c.zq, (size_t)c.n * 4));
   BFS_HIP(hipMalloc(&c.state, sizeof(LevelState)));
   BFS_HIP(hipMemset(c.state, 0, sizeof(LevelState)));
+  if (c.upper) {
+    BFS_HIP(hipMalloc(&c.fbits, (size_t)std::max<int64_t>(c.nwords, 1) * 8));
+    g->device_bytes += std::max<int64_t>(c.nwords, 1) * 8;
+  }
   if (c.symmetric) {
     BFS_HIP(hipMalloc(&c.mark, (size_t)std::max<int64_t>(c.nwords, 1) * 32));
     BFS_HIP(hipMemset(c.mark, 0, (size_t)std::max<int64_t>(c.nwords, 1) * 32));
@@ -906,6 +1170,7 @@ void csr_free(bfs_graph* g) {
   (void)hipFree(c.mark);
   (void)hipFree(c.hot_new);
   (void)hipFree(c.prev_bits);
+  (void)hipFree(c.fbits);
   (void)hipFree(c.state);
   if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
   if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
@@ -958,6 +1223,22 @@ int csr_check_symmetric(bfs_graph* g, hipStream_t s, int* symmetric) {
   (void)hipFree(d_bad);
   if (e != hipSuccess) return hip_fail(e, "symmetry check");
   *symmetric = h == 0;
+  return BFS_OK;
+}
+
+int csr_check_upper(bfs_graph* g, hipStream_t s, int* upper) {
+  CsrDev& c = g->csr;
+  *upper = 0;
+  int32_t* d_bad = nullptr;
+  BFS_HIP(hipMalloc(&d_bad, 4));
+  BFS_HIP(hipMemsetAsync(d_bad, 0, 4, s));
+  if (c.nnz > 0) k_check_upper<<<4096, 256, 0, s>>>(c.n, c.nnz, c.off, c.col, d_bad);
+  int32_t h = 0;
+  hipError_t e = hipMemcpyAsync(&h, d_bad, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_bad);
+  if (e != hipSuccess) return hip_fail(e, "upper-triangle check");
+  *upper = h == 0;
   return BFS_OK;
 }
 
@@ -1065,7 +1346,8 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   k_init<<<std::max(igrid, 1), ib, 0, s>>>(n_active, c.rpl, c.vis, c.nwords,
                                            mp.symmetric ? reinterpret_cast<uint4*>(c.mark)
                                                         : nullptr,
-                                           koff, root, krank, q, c.jstart, c.state, c.cbits);
+                                           koff, root, krank, q, c.jstart, c.state, c.cbits,
+                                           c.upper ? c.fbits : nullptr);
 
   // launch shapes: the claim expand and finish fill the chip with 256-thread
   // workgroups; the mark expand runs one 1024-thread workgroup per CU (its
@@ -1080,16 +1362,47 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   const unsigned long long cmask = (1ull << c.cbits) - 1;
   const bool prof = g->opt.profile > 0;
   const int probe = g->opt.cold_probe == 3 ? 0 : g->opt.cold_probe;
-  // One level: its launches; ev_base >= 0 brackets them with events
-  // ev_base .. ev_base + 3 (claim expand or level bitmap | mark expand or
-  // pull, after the previous push level's resolve | finish).
-  auto enqueue_level = [&](hipStream_t st, int64_t ev_base) -> int {
+  // the device level loop for small frontiers (not for upper-triangle
+  // graphs, whose levels also need the reverse search)
+  const bool small_on = !c.upper && g->opt.small_frontier >= 0;
+  SmallArgs sa;
+  sa.off = koff;
+  sa.col = kcol;
+  sa.vis = c.vis;
+  sa.rpl = c.rpl;
+  sa.mark = c.mark;
+  sa.inv = kinv;
+  sa.q = q;
+  sa.jstart = c.jstart;
+  sa.njs = c.njstart;
+  sa.st = c.state;
+  sa.cbits = c.cbits;
+  sa.mp = mp;
+  sa.max_f = g->opt.small_frontier > 0
+                 ? std::min<int64_t>(g->opt.small_frontier, small_max_frontier())
+                 : small_max_frontier();
+  sa.max_t = small_max_edges();
+  // One launch group: the device level loop (it runs as many small claim
+  // levels as it can, or returns at once), then one level's kernels for the
+  // level it leaves. ev_base >= 0 brackets them with events ev_base ..
+  // ev_base + 4 (loop | claim expand or level bitmap, and the reverse search
+  // of upper-triangle graphs | mark expand or pull, after the previous push
+  // level's resolve | finish).
+  auto enqueue_group = [&](hipStream_t st, int64_t ev_base) -> int {
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base], st));
+    if (small_on) small_levels_launch(st, sa);
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 1], st));
     k_expand<kExpandBlock><<<ge, kExpandBlock, 0, st>>>(koff, kcol, c.vis, c.rpl,
                                                         c.mark, q, c.jstart, c.njstart, c.zq,
                                                         c.state, c.cbits, mp, kinv,
-                                                        c.nwords, c.prev_bits);
-    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 1], st));
+                                                        c.nwords, c.prev_bits,
+                                                        c.upper ? c.fbits : nullptr,
+                                                        small_on ? 0 : 1);
+    if (c.upper)
+      k_reverse<kRevBlock><<<gf, kRevBlock, 0, st>>>(koff, kcol, c.vis, c.rpl, c.fbits, q,
+                                                     c.jstart, c.njstart, c.zq, c.state,
+                                                     c.cbits, c.n, c.nwords);
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 2], st));
     if (mp.symmetric) {
       MarkArgs a;
       a.col = kcol;
@@ -1114,18 +1427,41 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
       a.probe = probe;
       mark_expand_launch(gm, st, a);
     }
-    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 2], st));
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
     k_finish<kFinishBlock><<<gf, kFinishBlock, 0, st>>>(koff, c.vis, c.mark, q, c.jstart,
                                                         c.njstart, c.zq, c.state, c.cbits, c.n,
                                                         c.nwords, mp, c.hot_words, c.hot_new,
-                                                        gm);
-    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
+                                                        gm, c.upper ? c.fbits : nullptr);
+    if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 4], st));
     return BFS_OK;
   };
-  int64_t k = 0;
+  // the frontier the next group would expand: the counter of level
+  // k_expand - 1 (the host reads the counters and k_expand together)
+  int64_t k = 0;   // launch groups enqueued
+  static_assert(offsetof(LevelState, zcnt) + sizeof(LevelState::zcnt) <= 16 * 8,
+                "the host check reads the state's head into 16 words");
+  auto frontier_left = [&]() -> int {
+    BFS_HIP(hipMemcpyAsync(g->h_ctr, c.state, offsetof(LevelState, zcnt) + 12,
+                           hipMemcpyDeviceToHost, s));
+    BFS_HIP(wait_stream(s));
+    const char* head = reinterpret_cast<const char*>(g->h_ctr);
+    int32_t kx = 0;
+    std::memcpy(&kx, head + offsetof(LevelState, k_expand), 4);
+    // a search has at most n levels; every launch group enqueued after its
+    // last one advances the level number by one more
+    if (kx < 1 || (int64_t)kx > c.n + 2 + k)
+      return fail(BFS_ERR_DEVICE, "level loop did not terminate");
+    unsigned long long ctr = 0;
+    unsigned int z = 0;
+    std::memcpy(&ctr, head + offsetof(LevelState, ctr) + 8 * ((kx - 1) % 3), 8);
+    std::memcpy(&z, head + offsetof(LevelState, zcnt) + 4 * ((kx - 1) % 3), 4);
+    if (ctr & cmask) return 1;
+    // rowless frontier vertices of an upper-triangle graph
+    return (c.upper && z > 0) ? 1 : 0;
+  };
   if (g->opt.mode == 2) {
-    // Graph mode: kGraphLevels levels captured once per (outputs, policy,
-    // launch shapes) and replayed until a level finds an empty frontier;
+    // Graph mode: kGraphLevels launch groups captured once per (outputs,
+    // policy, launch shapes) and replayed until the frontier is empty;
     // replays between host checks double up to 8.
     GraphKey key{};
     key.mp_sym = mp.symmetric;
@@ -1135,7 +1471,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     key.grids[0] = ge;
     key.grids[1] = gm;
     key.grids[2] = gf;
-    key.grids[3] = 0;
+    key.grids[3] = small_on ? (int)sa.max_f : -1;
     key.mp_alpha = mp.pull_alpha;
     key.pad = 0;
     if (!c.gexec || std::memcmp(&key, &c.gkey, sizeof(key)) != 0) {
@@ -1144,7 +1480,7 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
       if (!c.cap_stream) BFS_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
       BFS_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
       int rc = BFS_OK;
-      for (int l = 0; l < kGraphLevels && rc == BFS_OK; ++l) rc = enqueue_level(c.cap_stream, -1);
+      for (int l = 0; l < kGraphLevels && rc == BFS_OK; ++l) rc = enqueue_group(c.cap_stream, -1);
       hipGraph_t graph = nullptr;
       const hipError_t ec = hipStreamEndCapture(c.cap_stream, &graph);
       if (rc != BFS_OK) {
@@ -1166,11 +1502,9 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
         BFS_HIP(hipGraphLaunch(c.gexec, s));
         k += kGraphLevels;
       }
-      BFS_HIP(hipMemcpyAsync(g->h_ctr, &c.state->ctr[k % 3], sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, s));
-      BFS_HIP(hipStreamSynchronize(s));
-      if ((*g->h_ctr & cmask) == 0) break;
-      if (k > c.n + 2) return fail(BFS_ERR_DEVICE, "level loop did not terminate");
+      const int left = frontier_left();
+      if (left < 0) return left;
+      if (!left) break;
       replays = std::min(replays * 2, 8);
     }
     g->profiled = prof ? 2 : 0;   // whole-run time only
@@ -1179,23 +1513,21 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     for (;;) {
       for (int b = 0; b < batch; ++b) {
         if (prof) {
-          const size_t need = 4 * (size_t)(k + 1) + 2;
+          const size_t need = 5 * (size_t)(k + 1) + 2;
           while (g->ev.size() < need) {
             hipEvent_t ev;
             BFS_HIP(hipEventCreate(&ev));
             g->ev.push_back(ev);
           }
         }
-        const int rc = enqueue_level(s, prof ? 2 + 4 * k : -1);
+        const int rc = enqueue_group(s, prof ? 2 + 5 * k : -1);
         if (rc != BFS_OK) return rc;
         ++k;
       }
       BFS_HIP(hipGetLastError());
-      BFS_HIP(hipMemcpyAsync(g->h_ctr, &c.state->ctr[k % 3], sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, s));
-      BFS_HIP(hipStreamSynchronize(s));
-      if ((*g->h_ctr & cmask) == 0) break;
-      if (k > c.n + 2) return fail(BFS_ERR_DEVICE, "level loop did not terminate");
+      const int left = frontier_left();
+      if (left < 0) return left;
+      if (!left) break;
     }
   }
   g->expand_launches = (int)k;
@@ -1209,9 +1541,43 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     BFS_HIP(hipMemcpyAsync(level, d_level, (size_t)c.n * 4, hipMemcpyDeviceToHost, s));
   g->last_stream = s;
   g->stats_valid = 1;
-  if (sync || host_parent || host_level) BFS_HIP(hipStreamSynchronize(s));
+  if (sync || host_parent || host_level) BFS_HIP(wait_stream(s));
   return BFS_OK;
 }
+
+namespace {
+
+float elapsed(const std::vector<hipEvent_t>& ev, size_t a, size_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ev[a], ev[b]) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.f;
+  }
+  return ms;
+}
+
+// Per launch group of the last profiled run: the level its level kernels
+// processed and the levels its device loop ran.
+struct Groups {
+  std::vector<int32_t> level, first, last;
+};
+
+int read_groups(bfs_graph* g, Groups* gr) {
+  const int ng = std::min(g->expand_launches, kLevelHist);
+  gr->level.assign((size_t)ng, 0);
+  gr->first.assign((size_t)ng, 1);
+  gr->last.assign((size_t)ng, 0);
+  if (ng == 0) return BFS_OK;
+  BFS_HIP(hipMemcpy(gr->level.data(), g->csr.state->grp_level, (size_t)ng * 4,
+                    hipMemcpyDeviceToHost));
+  BFS_HIP(hipMemcpy(gr->first.data(), g->csr.state->grp_first, (size_t)ng * 4,
+                    hipMemcpyDeviceToHost));
+  BFS_HIP(hipMemcpy(gr->last.data(), g->csr.state->grp_last, (size_t)ng * 4,
+                    hipMemcpyDeviceToHost));
+  return BFS_OK;
+}
+
+}  // namespace
 
 int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st) {
   LevelState h;
@@ -1228,38 +1594,52 @@ int csr_read_stats(bfs_graph* g, bfs_run_stats_t* st) {
   st->mark_levels = h.mark_levels;
   st->pull_levels = h.pull_levels;
   st->pull_edges = (int64_t)h.pull_edges;
+  st->small_levels = h.small_levels;
   if (g->profiled == 1) {
     // the mark kernel's time goes to mark_ms on push levels, pull_ms on
-    // pull levels (index k + 1 of the history is launch k)
-    const int nl = std::min(g->expand_launches, kLevelHist - 1);
-    std::vector<int32_t> kind((size_t)nl + 1, 0);
-    if (nl > 0)
-      BFS_HIP(hipMemcpy(kind.data(), g->csr.state->hist_mark, kind.size() * 4,
-                        hipMemcpyDeviceToHost));
-    double sum = 0.0, msum = 0.0, psum = 0.0;
-    for (int k = 0; k < g->expand_launches; ++k) {
-      float ms = 0.f, mm = 0.f;
-      BFS_HIP(hipEventElapsedTime(&ms, g->ev[2 + 4 * k], g->ev[4 + 4 * k]));
-      BFS_HIP(hipEventElapsedTime(&mm, g->ev[3 + 4 * k], g->ev[4 + 4 * k]));
-      sum += ms;
-      if (k < nl && kind[(size_t)k + 1] == 2) psum += mm;
+    // pull levels
+    Groups gr;
+    int rc = read_groups(g, &gr);
+    if (rc != BFS_OK) return rc;
+    std::vector<int32_t> kind(kLevelHist, 0);
+    BFS_HIP(hipMemcpy(kind.data(), g->csr.state->hist_mark, kind.size() * 4,
+                      hipMemcpyDeviceToHost));
+    double sum = 0.0, msum = 0.0, psum = 0.0, ssum = 0.0, fsum = 0.0;
+    for (int t = 0; t < g->expand_launches; ++t) {
+      const size_t b = 2 + 5 * (size_t)t;
+      ssum += elapsed(g->ev, b, b + 1);
+      sum += elapsed(g->ev, b + 1, b + 3);
+      const float mm = elapsed(g->ev, b + 2, b + 3);
+      const int lv = t < (int)gr.level.size() ? gr.level[(size_t)t] : 0;
+      if (lv > 0 && lv < kLevelHist && kind[(size_t)lv] == 2) psum += mm;
       else msum += mm;
+      fsum += elapsed(g->ev, b + 3, b + 4);
     }
     st->mark_ms = msum;
     st->pull_ms = psum;
     st->expand_ms = sum;
+    st->small_ms = ssum;
+    st->finish_ms = fsum;
   }
-  if (g->profiled) {
-    float tot = 0.f;
-    BFS_HIP(hipEventElapsedTime(&tot, g->ev[0], g->ev[1]));
-    st->total_ms = tot;
-  }
+  if (g->profiled) st->total_ms = elapsed(g->ev, 0, 1);
   return BFS_OK;
 }
 
 int csr_level_info(bfs_graph* g, bfs_level_info_t* out, int32_t capacity, int32_t* count) {
   BFS_HIP(hipStreamSynchronize(g->last_stream));
-  const int n = std::min<int>(std::min(capacity, g->expand_launches), kLevelHist - 1);
+  Groups gr;
+  int rc = read_groups(g, &gr);
+  if (rc != BFS_OK) return rc;
+  // levels with a record: every level a group's kernels or loop touched
+  int top = 0;
+  for (size_t t = 0; t < gr.level.size(); ++t) {
+    top = std::max(top, gr.level[t]);
+    if (gr.first[t] <= gr.last[t]) top = std::max(top, gr.last[t]);
+  }
+  // the launches after the last level find an empty frontier: one record
+  // for the level that found it
+  top = std::min(top + 1, kLevelHist - 1);
+  const int n = std::min<int>(capacity, top);
   std::vector<unsigned long long> hist((size_t)n + 1);
   std::vector<int32_t> hmark((size_t)n + 1);
   std::vector<unsigned long long> hpc((size_t)n + 1), hpe((size_t)n + 1);
@@ -1269,27 +1649,38 @@ int csr_level_info(bfs_graph* g, bfs_level_info_t* out, int32_t capacity, int32_
   BFS_HIP(hipMemcpy(hpc.data(), g->csr.state->hist_pc, hpc.size() * 8, hipMemcpyDeviceToHost));
   BFS_HIP(hipMemcpy(hpe.data(), g->csr.state->hist_pe, hpe.size() * 8, hipMemcpyDeviceToHost));
   const unsigned long long cmask = (1ull << g->csr.cbits) - 1;
+  // level -> the group whose level kernels processed it, and the group whose
+  // loop started at it
+  std::vector<int> by_kernels((size_t)n + 1, -1), loop_start((size_t)n + 1, -1);
+  for (size_t t = 0; t < gr.level.size(); ++t) {
+    const int lv = gr.level[t];
+    if (lv > 0 && lv <= n && by_kernels[(size_t)lv] < 0) by_kernels[(size_t)lv] = (int)t;
+    if (gr.first[t] <= gr.last[t] && gr.first[t] <= n) loop_start[(size_t)gr.first[t]] = (int)t;
+  }
   for (int i = 0; i < n; ++i) {
     const int k = i + 1;
     bfs_level_info_t& L = out[i];
+    L = bfs_level_info_t{};
     L.level = k;
     L.mark = hmark[(size_t)k];
     L.frontier = (int64_t)(hist[(size_t)k] & cmask);
     L.edges = (int64_t)(hist[(size_t)k] >> g->csr.cbits);
     L.pull_candidates = (int64_t)hpc[(size_t)k];
     L.pull_edges = (int64_t)hpe[(size_t)k];
-    float a = 0.f, m = 0.f, b = 0.f;
-    if (g->profiled == 1) {   // per-level events exist (not in graph mode)
-      BFS_HIP(hipEventElapsedTime(&a, g->ev[2 + 4 * i], g->ev[4 + 4 * i]));
-      BFS_HIP(hipEventElapsedTime(&m, g->ev[3 + 4 * i], g->ev[4 + 4 * i]));
-      BFS_HIP(hipEventElapsedTime(&b, g->ev[4 + 4 * i], g->ev[5 + 4 * i]));
+    if (g->profiled != 1) continue;   // per-launch events exist only level by level
+    const int t = by_kernels[(size_t)k];
+    if (t >= 0) {
+      const size_t b = 2 + 5 * (size_t)t;
+      const double m = elapsed(g->ev, b + 2, b + 3);
+      L.expand_ms = elapsed(g->ev, b + 1, b + 3);
+      L.mark_ms = L.mark == 2 ? 0.0 : m;
+      L.pull_ms = L.mark == 2 ? m : 0.0;
+      L.finish_ms = elapsed(g->ev, b + 3, b + 4);
     }
-    L.expand_ms = a;
-    L.mark_ms = L.mark == 2 ? 0.0 : m;
-    L.pull_ms = L.mark == 2 ? m : 0.0;
-    L.finish_ms = b;
+    const int tl = loop_start[(size_t)k];
+    if (tl >= 0) L.small_ms = elapsed(g->ev, 2 + 5 * (size_t)tl, 3 + 5 * (size_t)tl);
   }
-  *count = g->expand_launches;
+  *count = n;
   return BFS_OK;
 }
 

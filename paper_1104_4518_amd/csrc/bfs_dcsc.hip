@@ -2,35 +2,32 @@
 // stored as DCSC (section 4.1; Algorithm 3's SpMSV step, section 4.2).
 //
 // The product is the union of the columns A(:, k) for every k in the
-// frontier, each row keeping the minimum selected value. It is formed with
-// a sparse accumulator (SPA, section 4.2): a dense array of values, an
-// occupied bitmap, and an explicit ordering of the occupied rows. Here the
-// ordering comes from scanning the bitmap, which yields rows ascending
-// without a sort, and the same scan resets every touched SPA entry so the
-// accumulator is clean for the next call.
+// frontier, each row keeping the minimum selected value, emitted in
+// ascending row order. Two branches, as in section 4.2's polyalgorithm:
 //
-//   lookup   frontier index k -> position p of k in JC, via a bucket index
-//            over column ids (aux[b] = first p with JC[p] >= b * width)
-//            followed by a short search inside the bucket
-//   expand   rows IR[CP[p] .. CP[p+1]) of each found column
-//   combine  atomicMin into the SPA value, atomicOr into the occupied bits
-//   emit     bitmap scan -> ascending (row, value), SPA reset
-//
-// Very sparse frontiers take the other branch of the paper's polyalgorithm
-// (section 4.2: a SPA for denser products, a sort-based merge when the
-// product is small): one workgroup looks up the columns, writes the
-// products as packed (row, value) keys into LDS, sorts them (bitonic) and
-// keeps the first key of each row, so no work is proportional to nrows.
+//   binned accumulator (any frontier): the sparse accumulator of section 4.2
+//            split by rows. k_spmspv_bin looks up each frontier index k in JC
+//            (a bucket index over column ids, aux[b] = first p with JC[p] >=
+//            b * width, then a short search), expands the rows IR[CP[p] ..
+//            CP[p+1]) edge-balanced and appends every (row, value) product to
+//            the bin of its row (2^18 rows per bin); k_spmspv_reduce gives
+//            every bin one workgroup, whose LDS holds the bin's accumulator
+//            (a bitmap of the rows hit, ranked by a prefix over its words,
+//            and the minimum value of each ranked row) and which emits its
+//            rows ascending at the offset a chained scan over the bins gives.
+//            No global atomic per product, and no pass over the whole row
+//            space: the accumulator is cleared and scanned in LDS.
+//   sort-based merge (very sparse frontiers, below a tuned size): one
+//            workgroup looks up the columns, writes the products as packed
+//            (row, value) keys into LDS, sorts them (bitonic) and keeps the
+//            first key of each row.
 #include "bfs_internal.h"
 
 #include <algorithm>
+#include <vector>
 
 namespace bfsi {
 namespace {
-
-constexpr int kEmitBlock = 256;
-constexpr int kWordsPerThread = 8;
-constexpr int kWordsPerBlock = kEmitBlock * kWordsPerThread;
 
 __global__ void k_dcsc_validate(int32_t nrows, int32_t ncols, int32_t nzc, int64_t nnz,
                                 const int32_t* __restrict__ jc, const int32_t* __restrict__ cp,
@@ -70,133 +67,435 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-// One thread per frontier entry: lookup, expand, combine. Values are stored
-// order-preserving as (val ^ 0x80000000) so that unsigned atomicMin gives the
-// signed minimum.
-__global__ void k_spmspv_scatter(int64_t fnnz, const int32_t* __restrict__ fidx,
-                                 const int32_t* __restrict__ fval, int32_t ncols,
-                                 const int32_t* __restrict__ jc, const int32_t* __restrict__ cp,
-                                 const int32_t* __restrict__ ir, const int32_t* __restrict__ aux,
-                                 int shift, uint32_t* __restrict__ spa_val,
-                                 uint32_t* __restrict__ spa_occ,
-                                 unsigned long long* __restrict__ counters) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < fnnz; i += stride) {
-    const int32_t k = fidx[i];
-    if (k < 0 || k >= ncols || (i > 0 && fidx[i - 1] >= k)) {
-      atomicOr(&counters[1], 1ull);
-      continue;
-    }
-    const uint32_t key = (uint32_t)(fval ? fval[i] : k) ^ 0x80000000u;
-    const int64_t b = (int64_t)k >> shift;
-    int32_t lo = aux[b], hi = aux[b + 1];
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (jc[mid] < k) lo = mid + 1; else hi = mid;
-    }
-    if (lo >= aux[b + 1] || jc[lo] != k) continue;   // empty column
-    const int32_t q1 = cp[lo + 1];
-    for (int32_t qq = cp[lo]; qq < q1; ++qq) {
-      const int32_t r = ir[qq];
-      // products rarely share a row, so the min is not filtered by a read
-      // of the (large) value array and its result is not waited for
-      atomicMin(&spa_val[r], key);
-      const uint32_t bit = 1u << (r & 31);
-      if (!(spa_occ[r >> 5] & bit)) atomicOr(&spa_occ[r >> 5], bit);
-    }
-  }
-}
+// ---------------------------------------------------------------- binned product
+// The accumulator of section 4.2 split by rows. The output rows are cut into
+// bins of 2^kBinShift consecutive rows; bin b owns the slice
+// [bin_start[b], bin_start[b+1]) of a pair buffer, as long as the stored
+// entries of the block in those rows (a bound on the products one call can
+// put there, since every stored entry yields at most one product).
+//
+//   k_spmspv_bin     looks up the frontier's columns (bucket index + short
+//                    search), expands them edge-balanced, and
+//                    appends every product (row, value) to its row's bin:
+//                    products are staged in LDS, counted per bin, and each
+//                    workgroup reserves its slots of a bin with one atomic
+//                    per non-empty bin and staging round
+//   k_spmspv_reduce  one workgroup per bin: an LDS bitmap of the bin's rows
+//                    marks the rows hit; a prefix over its words ranks them;
+//                    the minimum of each row is taken in an LDS array indexed
+//                    by rank; the rows are emitted ascending. The output
+//                    offset of a bin is the number of rows hit by all bins
+//                    before it, found by a chained scan over the bins in
+//                    ascending order (each workgroup publishes its own count,
+//                    then its inclusive prefix; bins are taken in order of a
+//                    ticket counter, so a workgroup only waits for bins
+//                    already running).
+// Values travel order-preserving as (val ^ 0x80000000), so that an unsigned
+// minimum is the signed one.
+constexpr int kBinShift = 18;
+constexpr int kBinRows = 1 << kBinShift;
+constexpr int kBinWords = kBinRows / 32;
+constexpr int kMaxBins = 8192;          // 2^31 rows
+constexpr int kBinBlock = 1024;
+constexpr int kStage = 4096;            // products staged in LDS between bin rounds
+constexpr int kStagePer = kStage / kBinBlock;
+// frontier entries looked up together per thread: 8 while the per-bin
+// counters (8 B per bin, dynamic LDS) leave room, else 2
+constexpr int kWideEntries = 8, kNarrowEntries = 2;
+constexpr int kWideMaxBins = 4096;
+constexpr int kReduceBlock = 1024;
+constexpr int kValCap = 16384;          // rows of one bin reduced in LDS; more use the SPA
+// chained-scan flag word: epoch (30 bits) | status (2 bits) | count (32 bits)
+constexpr uint64_t kFlagAgg = 1, kFlagIncl = 2;
+constexpr long long kLookbackSpins = 1ll << 22;
 
-// Occupied-row count of each block's word range.
-__global__ __launch_bounds__(kEmitBlock) void k_spa_count(const uint32_t* __restrict__ occ,
-                                                          int64_t nwords,
-                                                          int64_t* __restrict__ blk_count) {
-  const int64_t w0 = blockIdx.x * (int64_t)kWordsPerBlock + threadIdx.x * kWordsPerThread;
-  int c = 0;
-#pragma unroll
-  for (int i = 0; i < kWordsPerThread; ++i)
-    if (w0 + i < nwords) c += __popc(occ[w0 + i]);
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
-  __shared__ int s[kEmitBlock / 64];
-  if (lane_id() == 0) s[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    long long t = 0;
-    for (int x = 0; x < kEmitBlock / 64; ++x) t += s[x];
-    blk_count[blockIdx.x] = t;
-  }
-}
+struct BinArgs {
+  int64_t fnnz;
+  const int32_t* fidx;
+  const int32_t* fval;
+  int32_t ncols;
+  const int32_t* jc;
+  const int32_t* cp;
+  const int32_t* ir;
+  const int32_t* aux;
+  int shift;
+  int32_t nbins;
+  const int64_t* bin_start;
+  int32_t* cursor;
+  unsigned long long* pairs;
+  unsigned long long* counters;
+  uint32_t epoch;
+};
 
-// Exclusive scan of the block counts (one block); total -> counters[0].
-__global__ void k_spa_scan(int64_t* __restrict__ blk_count, int64_t nblk,
-                           unsigned long long* __restrict__ counters) {
-  __shared__ long long s_carry;
-  __shared__ long long s_w[4];
-  if (threadIdx.x == 0) s_carry = 0;
-  __syncthreads();
-  for (int64_t base = 0; base < nblk; base += blockDim.x) {
-    const int64_t i = base + threadIdx.x;
-    const long long v = i < nblk ? blk_count[i] : 0;
-    const long long incl = wave_incl_scan(v);
-    const int wid = threadIdx.x >> 6;
-    if (lane_id() == 63) s_w[wid] = incl;
+// EPT frontier entries per thread form a sub-chunk of kBinBlock * EPT
+// consecutive entries; their lookups advance together (one load each per
+// step), then the sub-chunk's products are expanded edge-balanced into the
+// LDS stage, which is binned whenever it fills.
+template <int EPT>
+__global__ __launch_bounds__(kBinBlock) void k_spmspv_bin(BinArgs a) {
+  constexpr int WAVES = kBinBlock / 64;
+  constexpr int SUB = kBinBlock * EPT;
+  __shared__ int32_t s_pre[SUB];            // product prefix of the sub-chunk's entries
+  __shared__ int32_t s_q0[SUB];             // first stored entry of the entry's column
+  __shared__ int32_t s_row[kStage];         // staged products
+  __shared__ uint32_t s_kst[kStage];
+  __shared__ int s_w[WAVES];
+  extern __shared__ int32_t s_dyn[];
+  int32_t* s_hist = s_dyn;                  // products per bin this round (kept zero)
+  int32_t* s_base = s_dyn + a.nbins;        // reserved slot of the round's first product
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wid = tid >> 6;
+  for (int b = tid; b < a.nbins; b += kBinBlock) s_hist[b] = 0;
+  int staged = 0;   // products in the stage (the same in every thread)
+  bool bad = false;
+
+  // bins the staged products: per-bin ranks in LDS, one global reservation
+  // per non-empty bin, then the pairs written to their bins' slices
+  auto flush = [&](int S) {
     __syncthreads();
-    long long wb = 0, tot = 0;
-    for (int x = 0; x < (int)(blockDim.x >> 6); ++x) {
-      if (x < wid) wb += s_w[x];
-      tot += s_w[x];
+    int rk[kStagePer];
+#pragma unroll
+    for (int i = 0; i < kStagePer; ++i) {
+      const int j = tid + i * kBinBlock;
+      rk[i] = j < S ? atomicAdd(&s_hist[s_row[j] >> kBinShift], 1) : 0;
     }
-    const long long carry = s_carry;
-    if (i < nblk) blk_count[i] = carry + wb + incl - v;
     __syncthreads();
-    if (threadIdx.x == 0) s_carry = carry + tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) counters[0] = (unsigned long long)s_carry;
-}
-
-// Bitmap scan: rows ascending with their SPA values; resets SPA entries.
-__global__ __launch_bounds__(kEmitBlock) void k_spa_emit(
-    uint32_t* __restrict__ occ, int64_t nwords, uint32_t* __restrict__ spa_val,
-    const int64_t* __restrict__ blk_off, const unsigned long long* __restrict__ counters,
-    int64_t capacity, int32_t* __restrict__ out_idx, int32_t* __restrict__ out_val) {
-  const bool write = counters[0] <= (unsigned long long)capacity && counters[1] == 0ull;
-  const int64_t w0 = blockIdx.x * (int64_t)kWordsPerBlock + threadIdx.x * kWordsPerThread;
-  uint32_t words[kWordsPerThread];
-  int c = 0;
-#pragma unroll
-  for (int i = 0; i < kWordsPerThread; ++i) {
-    words[i] = (w0 + i < nwords) ? occ[w0 + i] : 0u;
-    c += __popc(words[i]);
-  }
-  const long long incl = wave_incl_scan(c);
-  __shared__ long long s_w[kEmitBlock / 64];
-  const int wid = threadIdx.x >> 6;
-  if (lane_id() == 63) s_w[wid] = incl;
-  __syncthreads();
-  long long wb = 0;
-  for (int x = 0; x < wid; ++x) wb += s_w[x];
-  long long pos = blk_off[blockIdx.x] + wb + incl - c;
-#pragma unroll
-  for (int i = 0; i < kWordsPerThread; ++i) {
-    uint32_t bits = words[i];
-    if (!bits) continue;
-    const int64_t wbase = (w0 + i) << 5;
-    while (bits) {
-      const int b = __ffs(bits) - 1;
-      bits &= bits - 1;
-      const int64_t r = wbase + b;
-      const uint32_t key = spa_val[r];
-      spa_val[r] = 0xFFFFFFFFu;
-      if (write) {
-        out_idx[pos] = (int32_t)r;
-        out_val[pos] = (int32_t)(key ^ 0x80000000u);
+    for (int b = tid; b < a.nbins; b += kBinBlock) {
+      const int h = s_hist[b];
+      if (h) {
+        s_base[b] = atomicAdd(&a.cursor[b], h);
+        s_hist[b] = 0;
       }
-      ++pos;
     }
-    occ[w0 + i] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kStagePer; ++i) {
+      const int j = tid + i * kBinBlock;
+      if (j < S) {
+        const int32_t row = s_row[j];
+        const int b = row >> kBinShift;
+        const int64_t st = a.bin_start[b];
+        const int64_t pos = st + (int64_t)s_base[b] + rk[i];
+        // a valid frontier never exceeds a bin's slice (each stored entry
+        // gives at most one product); a repeated column could
+        if (pos < a.bin_start[b + 1])
+          a.pairs[pos] = ((unsigned long long)(uint32_t)(row & (kBinRows - 1)) << 32) | s_kst[j];
+        else
+          bad = true;
+      }
+    }
+    __syncthreads();
+  };
+
+  const int64_t nsub = (a.fnnz + SUB - 1) / SUB;
+  for (int64_t c = blockIdx.x; c < nsub; c += gridDim.x) {
+    const int64_t c0 = c * SUB;
+    const int nE = (int)min((int64_t)SUB, a.fnnz - c0);
+    // lookup: thread t owns entries t*EPT .. t*EPT + EPT - 1
+    int32_t kk[EPT], lo[EPT], hi[EPT], bend[EPT];
+    {
+      const int64_t i0 = c0 + (int64_t)tid * EPT;
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) kk[j] = tid * EPT + j < nE ? a.fidx[i0 + j] : -1;
+      const int32_t prev = (tid * EPT < nE && i0 > 0) ? a.fidx[i0 - 1] : -1;
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        lo[j] = hi[j] = bend[j] = 0;
+        if (tid * EPT + j >= nE) continue;
+        const int32_t before = j ? kk[j - 1] : prev;
+        if (kk[j] < 0 || kk[j] >= a.ncols || before >= kk[j]) {
+          bad = true;
+          kk[j] = -1;
+          continue;
+        }
+        const int64_t bk = (int64_t)kk[j] >> a.shift;
+        lo[j] = a.aux[bk];
+        hi[j] = bend[j] = a.aux[bk + 1];
+      }
+    }
+    for (;;) {
+      bool any = false;
+#pragma unroll
+      for (int j = 0; j < EPT; ++j)
+        if (lo[j] < hi[j]) {
+          const int32_t mid = (lo[j] + hi[j]) >> 1;
+          if (a.jc[mid] < kk[j]) lo[j] = mid + 1; else hi[j] = mid;
+          any = true;
+        }
+      if (!any) break;
+    }
+    int32_t q0[EPT], len[EPT];
+    int mine = 0;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const bool found = kk[j] >= 0 && lo[j] < bend[j] && a.jc[lo[j]] == kk[j];
+      q0[j] = found ? lo[j] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int32_t p = q0[j];
+      q0[j] = p >= 0 ? a.cp[p] : 0;
+      len[j] = p >= 0 ? a.cp[p + 1] - q0[j] : 0;
+      mine += len[j];
+    }
+    // exclusive product prefix over the sub-chunk's entries (entry order)
+    const int incl = (int)wave_incl_scan((long long)mine);
+    if (lane == 63) s_w[wid] = incl;
+    __syncthreads();
+    int wb = 0, P = 0;
+#pragma unroll
+    for (int x = 0; x < WAVES; ++x) {
+      if (x < wid) wb += s_w[x];
+      P += s_w[x];
+    }
+    {
+      int ex = wb + incl - mine;
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int e = tid * EPT + j;
+        if (e < nE) {
+          s_pre[e] = ex;
+          s_q0[e] = q0[j];
+        }
+        ex += len[j];
+      }
+    }
+    __syncthreads();
+    // expand: product jj belongs to the last entry whose prefix is <= jj
+    // (entries without products share their successor's prefix); its value
+    // is read again from the frontier (a cached line)
+    for (int done = 0; done < P;) {
+      const int take = min(P - done, kStage - staged);
+      for (int j = tid; j < take; j += kBinBlock) {
+        const int jj = done + j;
+        int l = 0, h = nE - 1;
+        while (l < h) {
+          const int mid = (l + h + 1) >> 1;
+          if (s_pre[mid] <= jj) l = mid; else h = mid - 1;
+        }
+        const int64_t i = c0 + l;
+        s_row[staged + j] = a.ir[s_q0[l] + (jj - s_pre[l])];
+        s_kst[staged + j] = (uint32_t)(a.fval ? a.fval[i] : a.fidx[i]) ^ 0x80000000u;
+      }
+      staged += take;
+      done += take;
+      if (staged == kStage) {
+        flush(staged);
+        staged = 0;
+      }
+    }
+    __syncthreads();   // s_pre / s_q0 are rewritten by the next sub-chunk
   }
+  if (staged > 0) flush(staged);
+  if (__any(bad) && lane == 0) a.counters[1] = a.epoch;
+}
+
+struct ReduceArgs {
+  int32_t nbins;
+  const int64_t* bin_start;
+  int32_t* cursor;
+  const unsigned long long* pairs;
+  unsigned long long* chain;
+  int32_t* ticket;          // [0] bin ticket, [1] finished workgroups
+  uint32_t* spa_val;        // nrows, all ones between calls (bins over kValCap rows)
+  unsigned long long* counters;
+  uint32_t epoch;
+  int64_t capacity;
+  int32_t* out_idx;
+  int32_t* out_val;
+};
+
+__device__ __forceinline__ unsigned long long chain_word(uint32_t epoch, uint64_t status,
+                                                         uint32_t count) {
+  return ((unsigned long long)epoch << 34) | (status << 32) | count;
+}
+
+__global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
+  constexpr int WAVES = kReduceBlock / 64;
+  constexpr int WPT = kBinWords / kReduceBlock;   // bitmap words per thread
+  __shared__ uint32_t s_bits[kBinWords];
+  __shared__ int32_t s_wpre[kBinWords];
+  __shared__ uint32_t s_val[kValCap];
+  __shared__ int s_w[WAVES];
+  __shared__ int s_b, s_cnt, s_err;
+  __shared__ long long s_excl;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wid = tid >> 6;
+  if (tid == 0) {
+    s_b = atomicAdd(&a.ticket[0], 1);
+    s_err = a.counters[1] == a.epoch;
+    s_cnt = __hip_atomic_load(&a.cursor[s_b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  for (int w = tid; w < kBinWords; w += kReduceBlock) s_bits[w] = 0u;
+  __syncthreads();
+  const int b = s_b;
+  if (b >= a.nbins) {   // tickets out of step with the grid: report, touch nothing
+    if (tid == 0) a.counters[3] = a.epoch;
+    return;
+  }
+  const int64_t st = a.bin_start[b];
+  const int cnt = (int)min((int64_t)s_cnt, a.bin_start[b + 1] - st);
+  const bool err = s_err;
+  if (!err) {
+    for (int j = tid; j < cnt; j += kReduceBlock) {
+      const uint32_t r = (uint32_t)(a.pairs[st + j] >> 32);
+      atomicOr(&s_bits[r >> 5], 1u << (r & 31));
+    }
+  }
+  __syncthreads();
+  // rank of the first hit row of every word (block prefix over popcounts)
+  int c = 0;
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) c += __popc(s_bits[tid * WPT + i]);
+  const int incl = (int)wave_incl_scan((long long)c);
+  if (lane == 63) s_w[wid] = incl;
+  __syncthreads();
+  int wb = 0, U = 0;
+#pragma unroll
+  for (int x = 0; x < WAVES; ++x) {
+    if (x < wid) wb += s_w[x];
+    U += s_w[x];
+  }
+  {
+    int r = wb + incl - c;
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      s_wpre[tid * WPT + i] = r;
+      r += __popc(s_bits[tid * WPT + i]);
+    }
+  }
+  // chained scan: publish this bin's count, then find the rows of all bins
+  // before it (wave 0 looks back 64 bins at a time)
+  if (!err && wid == 0) {
+    if (lane == 0)
+      __hip_atomic_store(&a.chain[b], chain_word(a.epoch, kFlagAgg, (uint32_t)U),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long long excl = 0;
+    int j = b - 1;
+    long long spins = 0;
+    while (j >= 0) {
+      const int idx = j - lane;
+      unsigned long long f = chain_word(a.epoch, kFlagIncl, 0u);   // before bin 0: nothing
+      if (idx >= 0) f = __hip_atomic_load(&a.chain[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t fe = (uint32_t)(f >> 34);
+      const int status = fe == a.epoch ? (int)((f >> 32) & 3u) : 0;
+      const unsigned long long nr = wave_ballot(status == 0);
+      const unsigned long long inc = wave_ballot(status == 2);
+      const int first_nr = nr ? __ffsll((long long)nr) - 1 : 64;
+      const int first_inc = inc ? __ffsll((long long)inc) - 1 : 64;
+      if (first_nr < first_inc) {
+        // a bin not published yet: take the counts before it and wait
+        long long v = lane < first_nr ? (long long)(uint32_t)f : 0;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+        excl += v;
+        j -= first_nr;
+        if (++spins > kLookbackSpins) {
+          if (lane == 0) a.counters[3] = a.epoch;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      long long v = lane <= first_inc ? (long long)(uint32_t)f : 0;
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+      excl += v;
+      if (first_inc < 64) break;
+      j -= 64;
+    }
+    if (lane == 0) {
+      __hip_atomic_store(&a.chain[b], chain_word(a.epoch, kFlagIncl, (uint32_t)(excl + U)),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = excl;
+    }
+  }
+  __syncthreads();
+  if (!err) {
+    const long long excl = s_excl;
+    const int64_t row0 = (int64_t)b << kBinShift;
+    if (U <= kValCap) {
+      for (int i = tid; i < U; i += kReduceBlock) s_val[i] = 0xFFFFFFFFu;
+      __syncthreads();
+      for (int j = tid; j < cnt; j += kReduceBlock) {
+        const unsigned long long p = a.pairs[st + j];
+        const uint32_t r = (uint32_t)(p >> 32);
+        const int w = (int)(r >> 5);
+        const int rank = s_wpre[w] + __popc(s_bits[w] & ((1u << (r & 31)) - 1u));
+        atomicMin(&s_val[rank], (uint32_t)p);
+      }
+      __syncthreads();
+      for (int i = 0; i < WPT; ++i) {
+        const int w = i * kReduceBlock + tid;
+        uint32_t bits = s_bits[w];
+        int r = s_wpre[w];
+        while (bits) {
+          const int bit = __ffs(bits) - 1;
+          bits &= bits - 1;
+          const long long pos = excl + r;
+          if (pos < a.capacity) {
+            a.out_idx[pos] = (int32_t)(row0 + w * 32 + bit);
+            a.out_val[pos] = (int32_t)(s_val[r] ^ 0x80000000u);
+          }
+          ++r;
+        }
+      }
+    } else {
+      // more rows than the LDS array holds: the minimum goes through the
+      // block-wide SPA (all ones between calls), reset as it is emitted
+      for (int j = tid; j < cnt; j += kReduceBlock) {
+        const unsigned long long p = a.pairs[st + j];
+        atomicMin(&a.spa_val[row0 + (uint32_t)(p >> 32)], (uint32_t)p);
+      }
+      __threadfence();
+      __syncthreads();
+      for (int i = 0; i < WPT; ++i) {
+        const int w = i * kReduceBlock + tid;
+        uint32_t bits = s_bits[w];
+        int r = s_wpre[w];
+        while (bits) {
+          const int bit = __ffs(bits) - 1;
+          bits &= bits - 1;
+          const int64_t row = row0 + w * 32 + bit;
+          const uint32_t v =
+              __hip_atomic_load(&a.spa_val[row], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          a.spa_val[row] = 0xFFFFFFFFu;
+          const long long pos = excl + r;
+          if (pos < a.capacity) {
+            a.out_idx[pos] = (int32_t)row;
+            a.out_val[pos] = (int32_t)(v ^ 0x80000000u);
+          }
+          ++r;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.cursor[b] = 0;   // the bin's slice is empty for the next call
+    if (b == a.nbins - 1) a.counters[0] = err ? 0ull : (unsigned long long)(s_excl + U);
+    // the last workgroup to finish rewinds the tickets
+    if (atomicAdd(&a.ticket[1], 1) == a.nbins - 1) {
+      a.ticket[0] = 0;
+      a.ticket[1] = 0;
+    }
+  }
+}
+
+// Stored entries per bin of rows (setup): LDS histogram per workgroup.
+__global__ void k_bin_count(int64_t nnz, const int32_t* __restrict__ ir, int32_t nbins,
+                            unsigned long long* __restrict__ counts) {
+  __shared__ unsigned int s_h[kMaxBins];
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) s_h[b] = 0u;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nnz; q += stride)
+    atomicAdd(&s_h[ir[q] >> kBinShift], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+    if (s_h[b]) atomicAdd(&counts[b], (unsigned long long)s_h[b]);
 }
 
 // Sort path: frontier entries and products it can hold in LDS.
@@ -204,17 +503,6 @@ constexpr int kSortBlock = 1024;
 constexpr int kSortMaxF = 8192;
 constexpr int kSortMaxP = 8192;
 
-__device__ __forceinline__ int32_t dcsc_lookup(int32_t k, const int32_t* __restrict__ jc,
-                                               const int32_t* __restrict__ aux, int shift) {
-  const int64_t b = (int64_t)k >> shift;
-  int32_t lo = aux[b], hi = aux[b + 1];
-  const int32_t end = hi;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (jc[mid] < k) lo = mid + 1; else hi = mid;
-  }
-  return (lo < end && jc[lo] == k) ? lo : -1;
-}
 
 // Block-wide exclusive scan of one int per thread (kSortBlock threads).
 __device__ __forceinline__ int sort_block_scan(int v, int* s_w, int& total) {
@@ -406,19 +694,51 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   d.naux = ((int64_t)std::max(d.ncols, 1) >> shift) + 2;
   BFS_HIP(hipMalloc(&d.aux, (size_t)d.naux * 4));
   k_build_aux<<<1024, 256, 0, s>>>(d.jc, d.nzc, shift, d.naux, d.aux);
-  d.nwords = ((int64_t)d.nrows + 31) / 32;
+  // row bins: each owns a slice of the pair buffer as long as its stored entries
+  d.nbins = (int32_t)(((int64_t)std::max(d.nrows, 1) + kBinRows - 1) >> kBinShift);
+  BFS_HIP(hipMalloc(&d.bin_start, (size_t)(d.nbins + 1) * 8));
+  {
+    unsigned long long* cnt = nullptr;
+    BFS_HIP(hipMalloc(&cnt, (size_t)d.nbins * 8));
+    BFS_HIP(hipMemsetAsync(cnt, 0, (size_t)d.nbins * 8, s));
+    if (d.nnz > 0) k_bin_count<<<1024, 256, 0, s>>>(d.nnz, d.ir, d.nbins, cnt);
+    std::vector<unsigned long long> h((size_t)d.nbins);
+    hipError_t e = hipMemcpyAsync(h.data(), cnt, h.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(cnt);
+    if (e != hipSuccess) return hip_fail(e, "dcsc bin counts");
+    std::vector<int64_t> start((size_t)d.nbins + 1, 0);
+    for (int32_t b = 0; b < d.nbins; ++b) start[(size_t)b + 1] = start[(size_t)b] + (int64_t)h[(size_t)b];
+    BFS_HIP(hipMemcpy(d.bin_start, start.data(), start.size() * 8, hipMemcpyHostToDevice));
+  }
+  BFS_HIP(hipMalloc(&d.cursor, (size_t)d.nbins * 4));
+  BFS_HIP(hipMemsetAsync(d.cursor, 0, (size_t)d.nbins * 4, s));
+  BFS_HIP(hipMalloc(&d.chain, (size_t)d.nbins * 8));
+  BFS_HIP(hipMemsetAsync(d.chain, 0, (size_t)d.nbins * 8, s));
+  BFS_HIP(hipMalloc(&d.ticket, 2 * 4));
+  BFS_HIP(hipMemsetAsync(d.ticket, 0, 2 * 4, s));
+  BFS_HIP(hipMalloc(&d.pairs, (size_t)std::max<int64_t>(d.nnz, 1) * 8));
   BFS_HIP(hipMalloc(&d.spa_val, (size_t)std::max(d.nrows, 1) * 4));
-  BFS_HIP(hipMalloc(&d.spa_occ, (size_t)std::max<int64_t>(d.nwords, 1) * 4));
   k_fill_u32<<<1024, 256, 0, s>>>(d.spa_val, d.nrows, 0xFFFFFFFFu);
-  BFS_HIP(hipMemsetAsync(d.spa_occ, 0, (size_t)std::max<int64_t>(d.nwords, 1) * 4, s));
-  d.nblk = (d.nwords + kWordsPerBlock - 1) / kWordsPerBlock;
-  BFS_HIP(hipMalloc(&d.blk_count, (size_t)std::max<int64_t>(d.nblk, 1) * 8));
-  BFS_HIP(hipMalloc(&d.counters, 3 * sizeof(unsigned long long)));
-  BFS_HIP(hipMemsetAsync(d.counters, 0, 3 * sizeof(unsigned long long), s));
-  BFS_HIP(hipHostMalloc(&d.h_counters, 3 * sizeof(unsigned long long), hipHostMallocDefault));
+  BFS_HIP(hipMalloc(&d.counters, 4 * sizeof(unsigned long long)));
+  BFS_HIP(hipMemsetAsync(d.counters, 0, 4 * sizeof(unsigned long long), s));
+  BFS_HIP(hipHostMalloc(&d.h_counters, 4 * sizeof(unsigned long long), hipHostMallocDefault));
   BFS_HIP(hipStreamSynchronize(s));
+  // the binning kernel's per-bin counters live in dynamic LDS (8 B per bin)
+  (void)hipFuncSetAttribute((const void*)k_spmspv_bin<kNarrowEntries>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxBins * 8);
+  (void)hipFuncSetAttribute((const void*)k_spmspv_bin<kWideEntries>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kWideMaxBins * 8);
+  (void)hipGetLastError();
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) !=
+          hipSuccess || cus <= 0)
+    cus = 256;
+  d.grid_bin = cus;
+  d.epoch = 1;
   g->device_bytes += d.naux * 4 + (int64_t)std::max(d.nrows, 1) * 4 +
-                     std::max<int64_t>(d.nwords, 1) * 4 + std::max<int64_t>(d.nblk, 1) * 8 + 16;
+                     (int64_t)(d.nbins + 1) * 8 + (int64_t)d.nbins * 12 + 8 +
+                     std::max<int64_t>(d.nnz, 1) * 8 + 32;
   return BFS_OK;
 }
 
@@ -429,8 +749,11 @@ void dcsc_free(bfs_graph* g) {
   (void)hipFree(d.ir);
   (void)hipFree(d.aux);
   (void)hipFree(d.spa_val);
-  (void)hipFree(d.spa_occ);
-  (void)hipFree(d.blk_count);
+  (void)hipFree(d.bin_start);
+  (void)hipFree(d.cursor);
+  (void)hipFree(d.chain);
+  (void)hipFree(d.ticket);
+  (void)hipFree(d.pairs);
   (void)hipFree(d.counters);
   if (d.h_counters) (void)hipHostFree(d.h_counters);
   d = DcscDev{};
@@ -442,17 +765,21 @@ int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t 
   if (f->nnz > (int64_t)d.ncols) return fail(BFS_ERR_ARG, "frontier longer than ncols");
   if (out->capacity < 0 || (out->capacity > 0 && (!out->idx || !out->val)))
     return fail(BFS_ERR_ARG, "bad output vector");
-  BFS_HIP(hipMemsetAsync(d.counters, 0, 3 * sizeof(unsigned long long), s));
+  if (f->nnz == 0) {   // the empty product: nothing to look up or emit
+    out->nnz = 0;
+    return BFS_OK;
+  }
   // sort path for small frontiers (a product too large for LDS falls back)
   const int64_t sort_max = std::min<int64_t>(g->opt.spmspv_sort_max, kSortMaxF);
-  if (f->nnz > 0 && f->nnz <= sort_max) {
+  if (f->nnz <= sort_max) {
+    BFS_HIP(hipMemsetAsync(d.counters, 0, 3 * sizeof(unsigned long long), s));
     k_spmspv_sort<<<1, kSortBlock, 0, s>>>(f->nnz, f->idx, f->val, d.ncols, d.jc, d.cp, d.ir,
                                            d.aux, d.aux_shift, d.counters, out->capacity,
                                            out->idx, out->val);
     BFS_HIP(hipGetLastError());
     BFS_HIP(hipMemcpyAsync(d.h_counters, d.counters, 3 * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, s));
-    BFS_HIP(hipStreamSynchronize(s));
+    BFS_HIP(wait_stream(s));
     if (!d.h_counters[2]) {
       const int64_t cnt = (int64_t)d.h_counters[0];
       if (d.h_counters[1]) {
@@ -463,31 +790,67 @@ int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t 
       if (cnt > out->capacity) return fail(BFS_ERR_CAPACITY, "output capacity too small");
       return BFS_OK;
     }
-    BFS_HIP(hipMemsetAsync(d.counters, 0, 3 * sizeof(unsigned long long), s));
   }
-  if (f->nnz > 0) {
-    const int blk = 256;
-    const int64_t grid = std::min<int64_t>((f->nnz + blk - 1) / blk, 65536);
-    k_spmspv_scatter<<<(int)grid, blk, 0, s>>>(f->nnz, f->idx, f->val, d.ncols, d.jc, d.cp,
-                                                d.ir, d.aux, d.aux_shift, d.spa_val, d.spa_occ,
-                                                d.counters);
+  // binned path; every call has its own epoch, so the flags of earlier calls
+  // (chained scan, error words) need no clearing between calls
+  // (epochs start at 2: the sort path writes 0 or 1 into the error word)
+  if (++d.epoch >= (1u << 30)) {
+    BFS_HIP(hipMemsetAsync(d.chain, 0, (size_t)d.nbins * 8, s));
+    BFS_HIP(hipMemsetAsync(d.counters, 0, 4 * sizeof(unsigned long long), s));
+    d.epoch = 2;
   }
-  if (d.nwords > 0) {
-    k_spa_count<<<(int)d.nblk, kEmitBlock, 0, s>>>(d.spa_occ, d.nwords, d.blk_count);
-    k_spa_scan<<<1, 256, 0, s>>>(d.blk_count, d.nblk, d.counters);
-    k_spa_emit<<<(int)d.nblk, kEmitBlock, 0, s>>>(d.spa_occ, d.nwords, d.spa_val, d.blk_count,
-                                                   d.counters, out->capacity, out->idx,
-                                                   out->val);
+  BinArgs ba;
+  ba.fnnz = f->nnz;
+  ba.fidx = f->idx;
+  ba.fval = f->val;
+  ba.ncols = d.ncols;
+  ba.jc = d.jc;
+  ba.cp = d.cp;
+  ba.ir = d.ir;
+  ba.aux = d.aux;
+  ba.shift = d.aux_shift;
+  ba.nbins = d.nbins;
+  ba.bin_start = d.bin_start;
+  ba.cursor = d.cursor;
+  ba.pairs = d.pairs;
+  ba.counters = d.counters;
+  ba.epoch = d.epoch;
+  const size_t dyn = (size_t)d.nbins * 8;
+  if (d.nbins <= kWideMaxBins) {
+    const int64_t nsub = (f->nnz + kBinBlock * kWideEntries - 1) / (kBinBlock * kWideEntries);
+    k_spmspv_bin<kWideEntries>
+        <<<(int)std::min<int64_t>(nsub, d.grid_bin), kBinBlock, dyn, s>>>(ba);
+  } else {
+    const int64_t nsub =
+        (f->nnz + kBinBlock * kNarrowEntries - 1) / (kBinBlock * kNarrowEntries);
+    k_spmspv_bin<kNarrowEntries>
+        <<<(int)std::min<int64_t>(nsub, d.grid_bin), kBinBlock, dyn, s>>>(ba);
   }
+  ReduceArgs ra;
+  ra.nbins = d.nbins;
+  ra.bin_start = d.bin_start;
+  ra.cursor = d.cursor;
+  ra.pairs = d.pairs;
+  ra.chain = d.chain;
+  ra.ticket = d.ticket;
+  ra.spa_val = d.spa_val;
+  ra.counters = d.counters;
+  ra.epoch = d.epoch;
+  ra.capacity = out->capacity;
+  ra.out_idx = out->idx;
+  ra.out_val = out->val;
+  k_spmspv_reduce<<<d.nbins, kReduceBlock, 0, s>>>(ra);
   BFS_HIP(hipGetLastError());
-  BFS_HIP(hipMemcpyAsync(d.h_counters, d.counters, 2 * sizeof(unsigned long long),
+  BFS_HIP(hipMemcpyAsync(d.h_counters, d.counters, 4 * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, s));
-  BFS_HIP(hipStreamSynchronize(s));
-  const int64_t cnt = (int64_t)d.h_counters[0];
-  if (d.h_counters[1]) {
+  BFS_HIP(wait_stream(s));
+  if (d.h_counters[1] == d.epoch) {
     out->nnz = 0;
     return fail(BFS_ERR_ARG, "frontier indices must be strictly ascending and in [0, ncols)");
   }
+  if (d.h_counters[3] == d.epoch)
+    return fail(BFS_ERR_DEVICE, "spmspv: chained scan over the row bins did not complete");
+  const int64_t cnt = (int64_t)d.h_counters[0];
   out->nnz = cnt;
   if (cnt > out->capacity) return fail(BFS_ERR_CAPACITY, "output capacity too small");
   return BFS_OK;

@@ -20,6 +20,11 @@ void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
 
+// Waits for `s` by polling it (no blocking wait: a thread put to sleep by
+// the runtime wakes tens of microseconds after the work ends, which would
+// dominate calls that take microseconds). Returns the stream's error.
+hipError_t wait_stream(hipStream_t s);
+
 #define BFS_HIP(call)                                      \
   do {                                                     \
     hipError_t e_ = (call);                                \
@@ -63,6 +68,10 @@ struct LevelState {
   // 1 push mark level (its resolve runs in the next level's mark kernel),
   // 2 pull
   int32_t kind_cur, kind_prev;
+  // launch groups of this run (each: the device level loop, then one level's
+  // kernels), and the levels the device loop ran
+  int32_t groups;
+  int32_t small_levels;
   int32_t pad2;
   // input frontier counter of each level (profiling; levels < kLevelHist)
   unsigned long long hist[4096];
@@ -70,6 +79,11 @@ struct LevelState {
   // pull levels: vertices that searched, adjacencies they examined
   unsigned long long hist_pc[4096];
   unsigned long long hist_pe[4096];
+  // per launch group t (< kLevelHist): the level its level kernels processed
+  // (0 = none), and the first and last level its device loop ran
+  int32_t grp_level[4096];
+  int32_t grp_first[4096];
+  int32_t grp_last[4096];
 };
 constexpr int kLevelHist = 4096;
 
@@ -97,6 +111,10 @@ struct CsrDev {
   int32_t* zq = nullptr;         // reached vertices of out-degree 0 (per level)
   uint8_t* mark = nullptr;       // per-vertex touch marks (nwords * 32 bytes)
   int symmetric = 0;             // undirected with ascending adjacency (checked or asserted)
+  // upper-triangle storage: each undirected edge once, in the row of its
+  // smaller endpoint; the searched graph is its symmetric closure
+  int upper = 0;
+  uint32_t* fbits = nullptr;     // upper: frontier bitmaps of the two level parities
   // mark levels: hot prefix of the visited bitmap (words) and one slice of
   // newly touched hot bits per mark-path workgroup
   int hot_words = 0;
@@ -136,13 +154,20 @@ struct DcscDev {
   int aux_shift = 0;             // column bucket width = 2^aux_shift
   int64_t naux = 0;
   int32_t* aux = nullptr;        // aux[b] = first p with jc[p] >= b << aux_shift
-  // sparse accumulator (SPA): min values + occupied bitmap, kept clean
-  uint32_t* spa_val = nullptr;   // nrows, all 0xFFFFFFFF between calls
-  uint32_t* spa_occ = nullptr;   // ceil(nrows / 32) words, zero between calls
-  int64_t nwords = 0;
-  int64_t* blk_count = nullptr;  // per compaction block counts / offsets
-  int64_t nblk = 0;
-  unsigned long long* counters = nullptr;  // [0] out count, [1] error flag
+  // binned product: rows in bins of 2^18, bin b's products in
+  // pairs[bin_start[b] .. bin_start[b + 1]) ((row in bin) << 32 | value)
+  int32_t nbins = 0;
+  int64_t* bin_start = nullptr;  // nbins + 1: stored entries in the bins before b
+  int32_t* cursor = nullptr;     // products appended to each bin (zero between calls)
+  unsigned long long* pairs = nullptr;   // nnz
+  unsigned long long* chain = nullptr;   // chained-scan flag word per bin
+  int32_t* ticket = nullptr;     // [0] next bin, [1] finished workgroups (zero between calls)
+  uint32_t* spa_val = nullptr;   // nrows, all 0xFFFFFFFF between calls (bins too large for LDS)
+  uint32_t epoch = 0;            // calls of the binned path (flags carry it)
+  int grid_bin = 0;              // workgroups of the binning kernel
+  // [0] out count, [1] frontier error (epoch), [2] sort path: product too
+  // large, [3] chained-scan failure (epoch)
+  unsigned long long* counters = nullptr;
   unsigned long long* h_counters = nullptr;  // pinned host copy
 };
 
@@ -181,6 +206,8 @@ int csr_widen(const int32_t* d_src32, int64_t n1, int64_t* d_dst, hipStream_t s)
 void csr_free(bfs_graph* g);
 int csr_validate(bfs_graph* g, hipStream_t s);
 int csr_check_symmetric(bfs_graph* g, hipStream_t s, int* symmetric);
+// Every adjacency v of row u has v > u, rows strictly ascending.
+int csr_check_upper(bfs_graph* g, hipStream_t s, int* upper);
 // Builds the degree-ordered copy from the host row offsets.
 int csr_relabel(bfs_graph* g, const int64_t* host_off, hipStream_t s);
 int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStream_t s,

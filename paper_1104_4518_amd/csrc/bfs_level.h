@@ -28,6 +28,13 @@ constexpr int kSerialScan = 64;
 // "one level up" exactly.
 __device__ __forceinline__ uint8_t level_tag(int k) { return (uint8_t)(2 + k % 3); }
 
+// Map the edge tiles of the next level that start inside [e, e + d) to
+// queue entry j.
+__device__ __forceinline__ void map_tiles(int32_t* __restrict__ jstart, long long e, long long d,
+                                          int32_t j) {
+  for (long long w = (e + kTileJ - 1) / kTileJ; w * kTileJ < e + d; ++w) jstart[w] = j;
+}
+
 struct Queues {
   int32_t* qv[2];
   int64_t* qo[2];
@@ -113,6 +120,28 @@ struct MarkArgs {
   int probe;
 };
 int mark_expand_grid(int device);
+
+// The device level loop for small frontiers (bfs_small.hip): one workgroup
+// runs claim levels while a level's frontier holds at most max_f vertices and
+// max_t adjacencies (at most small_max_frontier() / small_max_edges()).
+struct SmallArgs {
+  const int64_t* off;
+  const int32_t* col;
+  uint32_t* vis;
+  unsigned long long* rpl;
+  uint8_t* mark;
+  const int32_t* inv;
+  Queues q;
+  int32_t* jstart;
+  int64_t njs;
+  LevelState* st;
+  int cbits;
+  MarkPolicy mp;
+  int64_t max_f, max_t;
+};
+void small_levels_launch(hipStream_t s, const SmallArgs& a);
+int64_t small_max_frontier();
+int64_t small_max_edges();
 void mark_expand_launch(int grid, hipStream_t s, const MarkArgs& a);
 
 }  // namespace bfsi

@@ -29,7 +29,7 @@
 namespace bfsi {
 namespace {
 
-template <int WG, int LDS_WORDS>
+template <int WG, int LDS_WORDS, int ROUND>
 __global__ __launch_bounds__(WG) void k_bfs_multi(MQuery* __restrict__ qs,
                                                   const int32_t* __restrict__ order, int32_t count,
                                                   int32_t* __restrict__ next_counter,
@@ -154,36 +154,56 @@ __global__ __launch_bounds__(WG) void k_bfs_multi(MQuery* __restrict__ qs,
         __syncthreads();
         const int rows = min(WG, F - c0);
         edges += (unsigned long long)tot;   // same value in every thread
-        for (long long e0 = 0; e0 < tot; e0 += WG) {
-          const long long e = e0 + tid;
-          bool own = false;
-          int32_t v = 0;
-          if (e < tot) {
-            int lo = 0, hi = rows - 1;
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
-            }
-            v = col[s_off[lo] + (e - s_pre[lo])];
-            const uint32_t uu = (uint32_t)s_u[lo];
-            const uint32_t bit = 1u << (v & 31);
-            const bool seen = lds ? (s_vis[v >> 5] & bit) != 0u : (gvis[v >> 5] & bit) != 0u;
-            if (!seen) {
-              uint32_t* pp = reinterpret_cast<uint32_t*>(parent) + v;
-              if (*pp > uu) {
-                const uint32_t old = __hip_atomic_fetch_min(pp, uu, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-                own = old == 0xFFFFFFFFu;
+        // the chunk's adjacencies, ROUND per thread per step with their
+        // loads in flight together (targets, visited bits, parents, claims)
+        for (long long e0 = 0; e0 < tot; e0 += (long long)WG * ROUND) {
+          int32_t v[ROUND];
+          uint32_t uu[ROUND];
+#pragma unroll
+          for (int i = 0; i < ROUND; ++i) {
+            const long long e = e0 + (long long)i * WG + tid;
+            v[i] = -1;
+            uu[i] = 0u;
+            if (e < tot) {
+              int lo = 0, hi = rows - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
               }
+              v[i] = col[s_off[lo] + (e - s_pre[lo])];
+              uu[i] = (uint32_t)s_u[lo];
             }
           }
-          if (own && level) level[v] = (int32_t)kn;
-          const unsigned long long m = wave_ballot(own);
-          if (m) {
-            int base = 0;
-            if (lane == 0) base = atomicAdd(&s_cnt, __popcll(m));
-            base = __shfl(base, 0, 64);
-            if (own) nxt[base + lanes_below(m)] = v;
+          bool fresh[ROUND];
+#pragma unroll
+          for (int i = 0; i < ROUND; ++i) {
+            fresh[i] = false;
+            if (v[i] >= 0) {
+              const uint32_t bit = 1u << (v[i] & 31);
+              fresh[i] = !(lds ? (s_vis[v[i] >> 5] & bit) : (gvis[v[i] >> 5] & bit));
+            }
+          }
+          uint32_t pcur[ROUND];
+#pragma unroll
+          for (int i = 0; i < ROUND; ++i)
+            pcur[i] = fresh[i] ? reinterpret_cast<uint32_t*>(parent)[v[i]] : 0u;
+#pragma unroll
+          for (int i = 0; i < ROUND; ++i) {
+            bool own = false;
+            if (fresh[i] && pcur[i] > uu[i]) {
+              uint32_t* pp = reinterpret_cast<uint32_t*>(parent) + v[i];
+              const uint32_t old = __hip_atomic_fetch_min(pp, uu[i], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+              own = old == 0xFFFFFFFFu;
+            }
+            if (own && level) level[v[i]] = (int32_t)kn;
+            const unsigned long long m = wave_ballot(own);
+            if (m) {
+              int base = 0;
+              if (lane == 0) base = atomicAdd(&s_cnt, __popcll(m));
+              base = __shfl(base, 0, 64);
+              if (own) nxt[base + lanes_below(m)] = v[i];
+            }
           }
         }
         __syncthreads();
@@ -215,13 +235,18 @@ __global__ __launch_bounds__(WG) void k_bfs_multi(MQuery* __restrict__ qs,
 
 }  // namespace
 
-const void* multi_kernel() { return (const void*)k_bfs_multi<kMultiWG, kLdsWords>; }
+constexpr int kMultiRound = 8;   // adjacencies per thread in flight
+
+const void* multi_kernel() {
+  return (const void*)k_bfs_multi<kMultiWG, kLdsWords, kMultiRound>;
+}
 
 int multi_launch(MQuery* d_qs, const int32_t* d_order, int32_t count, int32_t* d_counter,
                  int grid, bool pull, unsigned long long budget, char* ws_base,
                  int64_t ws_stride, int64_t ws_qbytes, hipStream_t s) {
   if (count <= 0) return BFS_OK;
-  k_bfs_multi<kMultiWG, kLdsWords><<<grid, kMultiWG, 0, s>>>(d_qs, d_order, count, d_counter,
+  k_bfs_multi<kMultiWG, kLdsWords, kMultiRound><<<grid, kMultiWG, 0, s>>>(
+      d_qs, d_order, count, d_counter,
                                                              pull ? 1 : 0, budget, ws_base,
                                                              ws_stride, ws_qbytes);
   BFS_HIP(hipGetLastError());

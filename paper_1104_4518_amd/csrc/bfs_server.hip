@@ -113,7 +113,9 @@ struct bfs_server {
   void run();
   void run_lane();
   bool is_large(const bfs_graph* g) const {
-    return large_nnz > 0 && g->csr.nnz >= large_nnz && g->csr.nnz >= 8 * g->csr.n;
+    // upper-triangle graphs have no multi-query path: always the lane
+    return g->csr.upper ||
+           (large_nnz > 0 && g->csr.nnz >= large_nnz && g->csr.nnz >= 8 * g->csr.n);
   }
 };
 
@@ -221,7 +223,7 @@ void bfs_server::run() {
     if (e == hipSuccess && rc == BFS_OK)
       e = hipMemcpyAsync(h_qs, d_qs, (size_t)hi * sizeof(bfsi::MQuery), hipMemcpyDeviceToHost,
                          stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = bfsi::wait_stream(stream);
     const double t = now_s();
     std::unique_lock<std::mutex> lk(mu);
     if (e != hipSuccess || rc != BFS_OK) {

@@ -84,9 +84,21 @@ def test_whole_bfs_push_bytes_formula():
 
 
 class _St:
-    def __init__(self, launches, expand, mark, pull):
+    def __init__(self, launches, expand, mark, pull, finish=3.0, small=0.25):
         self.expand_launches, self.expand_ms, self.mark_ms, self.pull_ms = \
             launches, expand, mark, pull
+        self.finish_ms, self.small_ms = finish, small
+
+
+def test_device_loop_levels_are_counted_once():
+    lv = [lvl(4, 1, 10), lvl(4, 10, 100), lvl(0, 50, 20000), lvl(4, 30, 60), lvl(4, 0, 0)]
+    nwords = 1 << 10
+    assert bench.small_levels_bytes(lv) == pytest.approx(
+        4.125 * 10 + 20 * 1 + 53 * 10 + 4.125 * 100 + 20 * 10 + 53 * 50
+        + 4.125 * 60 + 20 * 30 + 0)
+    # loop levels add nothing to the level kernels' counts
+    assert bench.claim_bytes(lv, nwords) == pytest.approx(4.125 * 20000 + 20 * 50 + 53 * 30)
+    assert bench.finish_bytes(lv, nwords) == pytest.approx(12 * 30)
 
 
 def test_kernel_split_attributes_times_and_bytes():
@@ -97,7 +109,8 @@ def test_kernel_split_attributes_times_and_bytes():
     assert sp["k_expand"]["launches"] == 12
     assert sp["k_expand"]["device_ms"] == pytest.approx(2 * 1.5)
     assert sp["k_expand_mark"]["device_ms"] == pytest.approx(2 * 1.5)
-    assert sp["k_finish"]["device_ms"] == pytest.approx(2 * 6 * 0.5)
+    assert sp["k_finish"]["device_ms"] == pytest.approx(2 * 3.0)
+    assert sp["k_small_levels"]["device_ms"] == pytest.approx(2 * 0.25)
     b = bench.mark_expand_bytes(lv) + bench.pull_bytes(lv, n_active)
     assert sp["k_expand_mark"]["bytes_per_launch"] == pytest.approx(2 * b / 12, rel=1e-6)
     assert sp["k_expand_mark"]["achieved_gbs"] == pytest.approx(2 * b / 3e-3 / 1e9, abs=0.01)

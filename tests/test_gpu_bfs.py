@@ -193,8 +193,15 @@ def test_profile_stats():
     r = int(graphgen.roots(g, 1, 2)[0])
     gpu_bfs(G, r)
     st = G.last_stats()
-    assert st.expand_launches >= st.levels >= 1
-    assert st.expand_ms > 0 and st.total_ms >= st.expand_ms
+    # launch groups (the device level loop, then one level's kernels): the
+    # levels either ran in the loop or each in a group of their own
+    lv = G.level_info()
+    by_kernels = sum(1 for L in lv if L["frontier"] > 0 and L["mark"] != 4)
+    by_loop = sum(1 for L in lv if L["frontier"] > 0 and L["mark"] == 4)
+    assert by_loop == st.small_levels and by_kernels + by_loop == st.levels >= 1
+    assert st.expand_launches >= by_kernels
+    assert st.expand_ms > 0 and st.total_ms >= st.expand_ms + st.small_ms
+    assert st.total_ms >= st.finish_ms > 0
 
 
 def test_errors():
@@ -333,3 +340,40 @@ def test_repeated_runs_many_roots_are_exact():
                 p, lv = gpu_bfs(G, int(r))
                 op, ol = ref[int(r)]
                 assert np.array_equal(p, op) and np.array_equal(lv, ol), (claim, rep, int(r))
+
+
+@pytest.mark.parametrize("limit", [-1, 1, 64, 1000, 8192])
+def test_device_level_loop_limits_give_identical_results(limit):
+    """The device level loop for small frontiers hands levels back to the
+    level kernels at different frontier sizes (off, 1, 64, 1000, 8192
+    vertices): every setting gives the oracle's arrays."""
+    graphs = [graphgen.rmat_csr(16, 16, 41), graphgen.grid_csr(96),
+              graphgen.er_csr(15, 4, 42), graphgen.from_edges(6, [(0, 1), (1, 2), (2, 3)])]
+    for g in graphs:
+        G = graph_on_device(g)
+        G.set_options(small_frontier=limit)
+        for r in (list(graphgen.roots(g, 3, 43)) if g.n > 6 else [0, 3, 5]):
+            say(f"loop limit {limit} n {g.n} root {r}")
+            assert_bfs_equal(g, G, int(r))
+            st = G.last_stats()
+            if limit == -1:
+                assert st.small_levels == 0
+
+
+def test_grid2048_corner_runs_in_the_device_loop():
+    """4,094 levels of at most 2,048 vertices, and the level that finds the
+    far corner's neighbours all visited: every one runs in the device loop,
+    and the level record lists each as a loop level."""
+    g = graphgen.grid_csr(2048)
+    G = graph_on_device(g)
+    G.set_options(profile=1)
+    say("grid2048 root 0")
+    _, ol = assert_bfs_equal(g, G, 0)
+    st = G.last_stats()
+    assert ol.max() == 4094 and st.depth == 4094
+    assert st.small_levels == st.levels == 4095
+    lv = G.level_info()
+    assert [L["level"] for L in lv[:3]] == [1, 2, 3]
+    assert all(L["mark"] == 4 for L in lv[:4095])
+    assert lv[0]["frontier"] == 1 and lv[1]["frontier"] == 2
+    G.set_options(profile=-1)

@@ -176,4 +176,4 @@ def test_claim_level_with_many_new_vertices_from_few_edges():
         say(f"star + random, root {r}")
         assert_bfs_equal(g, G, r)
     info = [L for L in G.level_info() if L["frontier"] > 0]
-    assert all(L["mark"] in (0, 3) for L in info)
+    assert all(L["mark"] in (0, 3, 4) for L in info)

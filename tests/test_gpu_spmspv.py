@@ -22,9 +22,9 @@ def block_on_device(b, sort_max=0):
     return Gb
 
 
-# both branches of the polyalgorithm: -1 = sparse accumulator only,
+# both branches of the polyalgorithm: -1 = the binned accumulator only,
 # 8192 = the sort path for frontiers up to 8192 entries
-PATHS = pytest.mark.parametrize("path", [-1, 8192], ids=["spa", "sort"])
+PATHS = pytest.mark.parametrize("path", [-1, 8192], ids=["binned", "sort"])
 
 
 def check(Gb, blk, fidx, fval=None):
@@ -126,16 +126,78 @@ def test_generated_block_scale20(density, path):
 
 
 def test_config_share_2pow26():
-    """The benchmarked share: 2^26 x 2^26, 16.8M uniform nonzeros, one call per
-    density and a repeat at 10% (the accumulator must reset between calls)."""
+    """The benchmarked share: 2^26 x 2^26, 16.8M uniform nonzeros (256 row
+    bins), ten calls at each of the four densities, element-wise against the
+    oracle (the bins, their cursors and the chained scan are reused by every
+    call). The share's own tuned switch decides the branch, as in the
+    benchmark."""
     blk = graphgen.dcsc_block(26, 1 << 24, 4)
     Gb = block_on_device(blk)
-    for i, density in enumerate([0.0001, 0.001, 0.01, 0.1, 0.1]):
+    Gb.tune()
+    call = 0
+    for density in (0.0001, 0.001, 0.01, 0.1):
         k = int(density * (1 << 26))
-        f = graphgen.frontier_sample(26, k, 4000 + i)
-        say(f"share 2^26 density {density}")
-        out = check(Gb, blk, f)
-        assert out.size > 0
+        for rep in range(10):
+            f = graphgen.frontier_sample(26, k, 4000 + call)
+            call += 1
+            say(f"share 2^26 density {density} call {rep}")
+            out = check(Gb, blk, f)
+            assert out.size > 0
+
+
+def test_bins_over_the_lds_accumulator_use_the_block_spa():
+    """One bin of 2^18 rows receiving more distinct rows than its LDS
+    accumulator ranks (16384): those bins take the minimum through the
+    block-wide accumulator and must leave it clean; neighbouring bins stay in
+    LDS. Values repeat so many rows see several candidates."""
+    rng = np.random.default_rng(21)
+    nr, nc, nnz = 3 * (1 << 18) + 5, 1 << 17, 1 << 21
+    rows = rng.integers(0, nr, nnz)
+    # crowd the middle bin: most entries land in rows [2^18, 2^19)
+    crowd = rng.random(nnz) < 0.7
+    rows[crowd] = rng.integers(1 << 18, 1 << 19, int(crowd.sum()))
+    cols = rng.integers(0, nc, nnz)
+    key = np.unique(cols.astype(np.int64) << 32 | rows.astype(np.int64))
+    c, r = (key >> 32).astype(np.int64), (key & 0xFFFFFFFF).astype(np.int32)
+    jc, start = np.unique(c, return_index=True)
+    blk = graphgen.DCSCBlock(nr, nc, jc.astype(np.int32),
+                             np.append(start, r.size).astype(np.int32), r)
+    Gb = block_on_device(blk, -1)
+    for rep, k in enumerate((nc // 2, 3000, nc // 2, nc)):
+        f = np.sort(rng.choice(nc, size=k, replace=False)).astype(np.int32)
+        fv = rng.integers(-50, 50, size=k).astype(np.int32) if rep != 1 else None
+        say(f"crowded bin rep {rep} k {k}")
+        out = check(Gb, blk, f, fv)
+        if rep == 0:
+            mid = ((out >= (1 << 18)) & (out < (1 << 19))).sum()
+            assert mid > 16384   # the LDS accumulator's limit is exceeded
+
+
+def test_many_bins_and_products_in_one_bin():
+    """64 row bins, a frontier whose products all fall into one late bin (the
+    chained scan must carry the empty bins before it), then products spread
+    over every bin; and repeated calls that alternate between them."""
+    rng = np.random.default_rng(5)
+    nr, nc = 64 * (1 << 18), 5000
+    rows_a = rng.integers(60 * (1 << 18), 61 * (1 << 18), 20000)   # one bin
+    rows_b = rng.integers(0, nr, 20000)
+    cols = np.concatenate([rng.integers(0, nc // 2, 20000), rng.integers(nc // 2, nc, 20000)])
+    rows = np.concatenate([rows_a, rows_b])
+    key = np.unique(cols.astype(np.int64) << 32 | rows.astype(np.int64))
+    c, r = (key >> 32).astype(np.int64), (key & 0xFFFFFFFF).astype(np.int32)
+    jc, start = np.unique(c, return_index=True)
+    blk = graphgen.DCSCBlock(nr, nc, jc.astype(np.int32),
+                             np.append(start, r.size).astype(np.int32), r)
+    Gb = block_on_device(blk, -1)
+    first = np.arange(0, nc // 2, dtype=np.int32)
+    second = np.arange(nc // 2, nc, dtype=np.int32)
+    for rep in range(3):
+        say(f"one late bin rep {rep}")
+        out = check(Gb, blk, first)
+        assert out.size > 0 and out.min() >= 60 * (1 << 18) and out.max() < 61 * (1 << 18)
+        say(f"all bins rep {rep}")
+        check(Gb, blk, second)
+        check(Gb, blk, np.arange(nc, dtype=np.int32))
 
 
 def test_sort_path_limits_and_fallback():

@@ -25,6 +25,7 @@ def test_tune_csr_choices_cache_and_results(tmp_path):
     assert len(lines) == 1 and " csr n=16384 " in lines[0] and "min_frontier=" in lines[0]
     assert "pull_alpha=" in lines[0] and "claim_threshold=" in lines[0]
     assert o.claim_threshold in (0, g.nnz // 16)
+    assert o.small_frontier in (8192, 1024, -1) and "small_frontier=" in lines[0]
     for r in graphgen.roots(g, 3, 5):
         say(f"tuned rmat14 root {r}")
         assert_bfs_equal(g, G, r)
@@ -33,8 +34,9 @@ def test_tune_csr_choices_cache_and_results(tmp_path):
     G2.tune(str(cache))
     o2 = G2.get_options()
     assert (o2.grid_blocks, o2.batch_levels, o2.claim_min_frontier, o2.pull_alpha,
-            o2.claim_threshold) == \
-        (o.grid_blocks, o.batch_levels, o.claim_min_frontier, o.pull_alpha, o.claim_threshold)
+            o2.claim_threshold, o2.small_frontier) == \
+        (o.grid_blocks, o.batch_levels, o.claim_min_frontier, o.pull_alpha, o.claim_threshold,
+         o.small_frontier)
     assert len(cache.read_text().splitlines()) == 1
 
 
@@ -53,3 +55,18 @@ def test_tune_dcsc_polyalgorithm_switch(tmp_path):
         gi, gv = gpu_spmspv(Gb, f)
         oi, ov = oracle.spmspv_block(blk, f)
         assert np.array_equal(gi, oi) and np.array_equal(gv, ov)
+
+
+def test_tune_csr_repeats_its_choice():
+    """Three tunings of one graph (no cache) pick the same options: a value
+    replaces the current one only when it is clearly faster."""
+    g = graphgen.rmat_csr(18, 16, 44)
+    G = B.Graph.from_csr(g.n, g.off, g.col)
+    picks = []
+    for i in range(3):
+        say(f"tune rmat18 pass {i}")
+        G.tune()
+        o = G.get_options()
+        picks.append((o.grid_blocks, o.batch_levels, o.claim_min_frontier, o.pull_alpha,
+                      o.claim_threshold, o.small_frontier))
+    assert picks[0] == picks[1] == picks[2], picks

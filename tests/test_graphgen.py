@@ -95,3 +95,19 @@ def test_frontier_sample():
     assert f.size == 1000 and np.all(np.diff(f) > 0) and f.max() < (1 << 20)
     assert np.array_equal(f, graphgen.frontier_sample(20, 1000, 3))
     assert graphgen.frontier_sample(20, 0, 3).size == 0
+
+
+def test_upper_csr_stores_each_edge_once_and_closes_to_the_graph():
+    g = graphgen.rmat_csr(10, 16, 3)
+    u = graphgen.upper_csr(g)
+    assert u.nnz * 2 == g.nnz   # symmetric, no self-loops: every edge in two rows
+    src = np.repeat(np.arange(u.n), np.diff(u.off))
+    assert (u.col > src).all()
+    for r in range(u.n):   # rows ascending
+        row = u.col[u.off[r]:u.off[r + 1]]
+        assert (np.diff(row) > 0).all()
+    # the symmetric closure of the stored half is the graph
+    a = set(zip(src.tolist(), u.col.tolist()))
+    closure = a | {(v, w) for (w, v) in a}
+    gsrc = np.repeat(np.arange(g.n), np.diff(g.off))
+    assert closure == set(zip(gsrc.tolist(), g.col.tolist()))

@@ -303,6 +303,22 @@ int bfs_spmspv(bfs_graph_t* block, const bfs_svec_t* frontier, bfs_svec_t* out,
 int bfs_run_2d(bfs_graph_t* const* shares, int32_t pr, int32_t pc, int64_t n, int32_t root,
                int32_t* parent, int32_t* level, void* hip_stream);
 
+/*
+ * bfs_run_2d for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search and results as bfs_run_2d, with its per-run workspace taken from a
+ * fixed device array inside the library (26 MiB per GPU, held until the
+ * process ends) instead of hipMalloc, and its host read-backs into stack
+ * memory instead of pinned buffers. It calls no allocator. Limits: n <=
+ * 2^20, pc <= 256, pr * pc <= 1024 (BFS_ERR_CAPACITY / BFS_ERR_UNSUPPORTED
+ * beyond them). Every call on one GPU uses that GPU's one array: calls that
+ * overlap on the same GPU (other threads or streams) race and must be
+ * serialised by the caller. The shares' own accumulators are used as in
+ * bfs_run_2d. Synchronous on `hip_stream`.
+ */
+int bfs_run_2d_noalloc(bfs_graph_t* const* shares, int32_t pr, int32_t pc, int64_t n,
+                       int32_t root, int32_t* parent, int32_t* level, void* hip_stream);
+
 /* ---------------------------------------------------------------- batches */
 
 /*

@@ -141,6 +141,7 @@ def load(build_if_missing: bool = True):
         "bfs_run_batch": [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_i32), ctypes.POINTER(_vp),
                           ctypes.POINTER(_vp), _vp],
         "bfs_run_2d": [ctypes.POINTER(_vp), _i32, _i32, _i64, _i32, _vp, _vp, _vp],
+        "bfs_run_2d_noalloc": [ctypes.POINTER(_vp), _i32, _i32, _i64, _i32, _vp, _vp, _vp],
         "bfs_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)],
         "bfs_server_submit": [_vp, _vp, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)],
         "bfs_server_poll": [_vp, ctypes.c_uint64, ctypes.POINTER(Result)],
@@ -350,6 +351,15 @@ def run_2d(shares: Sequence[Graph], pr: int, pc: int, n: int, root: int, parent,
     hs = (_vp * cnt)(*[g.handle for g in shares])
     _check(load().bfs_run_2d(hs, int(pr), int(pc), int(n), int(root), _ptr(parent), _ptr(level),
                              _stream(stream)), "bfs_run_2d")
+
+
+def run_2d_noalloc(shares: Sequence[Graph], pr: int, pc: int, n: int, root: int, parent,
+                   level=None, stream=None) -> None:
+    """bfs_run_2d on the library's fixed device workspace (no allocation)."""
+    cnt = len(shares)
+    hs = (_vp * cnt)(*[g.handle for g in shares])
+    _check(load().bfs_run_2d_noalloc(hs, int(pr), int(pc), int(n), int(root), _ptr(parent),
+                                     _ptr(level), _stream(stream)), "bfs_run_2d_noalloc")
 
 
 class Server:

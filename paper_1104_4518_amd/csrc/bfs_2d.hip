@@ -162,26 +162,6 @@ __global__ __launch_bounds__(kApplyBlock) void k2_apply(
   }
 }
 
-struct Ws2d {
-  int32_t *f = nullptr, *fnext = nullptr, *fl = nullptr, *cand = nullptr;
-  int32_t *oidx = nullptr, *oval = nullptr;
-  uint32_t* newbit = nullptr;
-  int64_t *bounds = nullptr, *blk = nullptr, *total = nullptr;
-  int64_t* h = nullptr;   // pinned: bounds (pc + 1) then the count
-  ~Ws2d() {
-    (void)hipFree(f);
-    (void)hipFree(fnext);
-    (void)hipFree(fl);
-    (void)hipFree(cand);
-    (void)hipFree(oidx);
-    (void)hipFree(oval);
-    (void)hipFree(newbit);
-    (void)hipFree(bounds);
-    (void)hipFree(blk);
-    (void)hipFree(total);
-    if (h) (void)hipHostFree(h);
-  }
-};
 
 bool on_device(const void* p) {
   hipPointerAttribute_t a;
@@ -192,21 +172,61 @@ bool on_device(const void* p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
-}  // namespace
-}  // namespace bfsi
+// Device pointers of one run's workspace (about 24 n bytes).
+struct View2d {
+  int32_t *f, *fnext, *fl, *cand, *oidx, *oval;
+  uint32_t* newbit;
+  int64_t *bounds, *blk, *total;
+};
 
-using namespace bfsi;
+// Bytes of that workspace, carved in 256-byte aligned pieces.
+int64_t ws2d_bytes(int64_t n, int64_t max_rows, int pc) {
+  auto al = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t nwords = (n + 31) / 32;
+  const int64_t nblk = (nwords + kApplyPerBlock - 1) / kApplyPerBlock;
+  return 4 * al(n * 4) + 2 * al(max_rows * 4) + al(nwords * 4) + al((int64_t)(pc + 1) * 8) +
+         al(std::max<int64_t>(nblk, 1) * 8) + al(8);
+}
 
-extern "C" int bfs_run_2d(bfs_graph_t* const* shares, int32_t pr, int32_t pc, int64_t n,
-                          int32_t root, int32_t* parent, int32_t* level, void* hip_stream) {
+View2d ws2d_carve(char* base, int64_t n, int64_t max_rows, int pc) {
+  auto al = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t nwords = (n + 31) / 32;
+  const int64_t nblk = (nwords + kApplyPerBlock - 1) / kApplyPerBlock;
+  View2d v;
+  char* p = base;
+  auto take = [&](int64_t bytes) {
+    char* q = p;
+    p += al(bytes);
+    return q;
+  };
+  v.f = reinterpret_cast<int32_t*>(take(n * 4));
+  v.fnext = reinterpret_cast<int32_t*>(take(n * 4));
+  v.fl = reinterpret_cast<int32_t*>(take(n * 4));
+  v.cand = reinterpret_cast<int32_t*>(take(n * 4));
+  v.oidx = reinterpret_cast<int32_t*>(take(max_rows * 4));
+  v.oval = reinterpret_cast<int32_t*>(take(max_rows * 4));
+  v.newbit = reinterpret_cast<uint32_t*>(take(nwords * 4));
+  v.bounds = reinterpret_cast<int64_t*>(take((int64_t)(pc + 1) * 8));
+  v.blk = reinterpret_cast<int64_t*>(take(std::max<int64_t>(nblk, 1) * 8));
+  v.total = reinterpret_cast<int64_t*>(take(8));
+  return v;
+}
+
+constexpr int kMaxShares = 1024;
+
+// Checks the arguments of a 2D run and collects the shares (row-major) and
+// their largest row count; every share must have the shape of its block.
+int check_2d(bfs_graph_t* const* shares, int32_t pr, int32_t pc, int64_t n, int32_t root,
+             int32_t* parent, int32_t* level, bfs_graph** all, int64_t* max_rows) {
   if (!shares || !parent || pr < 1 || pc < 1 || n < 1 || n >= ((int64_t)1 << 31))
     return fail(BFS_ERR_ARG, "bad arguments to bfs_run_2d");
+  if ((int64_t)pr * pc > kMaxShares)
+    return fail(BFS_ERR_UNSUPPORTED, "at most 1024 shares in a 2D grid");
   if (root < 0 || (int64_t)root >= n) return fail(BFS_ERR_ARG, "root out of range");
   const int64_t R = (n + pr - 1) / pr, C = (n + pc - 1) / pc;
   if ((int64_t)(pr - 1) * R >= n || (int64_t)(pc - 1) * C >= n)
     return fail(BFS_ERR_ARG, "every share needs at least one row and one column");
-  std::vector<bfs_graph*> all;
-  int64_t max_rows = 1;
+  *max_rows = 1;
   for (int i = 0; i < pr; ++i)
     for (int j = 0; j < pc; ++j) {
       bfs_graph* g = shares[(size_t)i * pc + j];
@@ -214,73 +234,163 @@ extern "C" int bfs_run_2d(bfs_graph_t* const* shares, int32_t pr, int32_t pc, in
       const int64_t nr = std::min<int64_t>(R, n - i * R), nc = std::min<int64_t>(C, n - j * C);
       if (g->dcsc.nrows != nr || g->dcsc.ncols != nc)
         return fail(BFS_ERR_ARG, "share shape does not match the p_r x p_c split of n");
-      all.push_back(g);
-      max_rows = std::max<int64_t>(max_rows, nr);
+      all[(size_t)i * pc + j] = g;
+      *max_rows = std::max<int64_t>(*max_rows, nr);
     }
-  std::vector<bfs_graph*> sorted = all;
-  std::sort(sorted.begin(), sorted.end());
-  if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+  const int cnt = pr * pc;
+  std::sort(all, all + cnt);
+  if (std::adjacent_find(all, all + cnt) != all + cnt)
     return fail(BFS_ERR_ARG, "the same handle appears twice in the share grid");
   if (!on_device(parent) || (level && !on_device(level)))
     return fail(BFS_ERR_ARG, "bfs_run_2d needs device output arrays");
+  return BFS_OK;
+}
+
+// The level loop of a 2D run on a carved workspace; h holds pc + 2 host
+// int64 (the column bounds, then the frontier size). Allocates nothing.
+int run_2d_core(bfs_graph_t* const* shares, int32_t pr, int32_t pc, int64_t n, int32_t root,
+                int32_t* parent, int32_t* level, int64_t max_rows, const View2d& w, int64_t* h,
+                hipStream_t s) {
+  const int64_t R = (n + pr - 1) / pr, C = (n + pc - 1) / pc;
+  const int64_t nwords = (n + 31) / 32;
+  const int64_t nblk = (nwords + kApplyPerBlock - 1) / kApplyPerBlock;
+  const int ib = 256;
+  const int igrid = (int)std::min<int64_t>((n + ib - 1) / ib, 8192);
+  int32_t* f = w.f;
+  int32_t* fnext = w.fnext;
+  k2_init<<<igrid, ib, 0, s>>>(n, parent, level, w.cand, w.newbit, nwords, root, f);
+  BFS_HIP(hipGetLastError());
+  int64_t F = 1;
+  for (int32_t k = 1; F > 0; ++k) {
+    const int sgrid = (int)std::min<int64_t>((F + ib - 1) / ib, 4096);
+    k2_split<<<sgrid, ib, 0, s>>>(f, F, C, pc, w.fl, w.bounds);
+    BFS_HIP(hipMemcpyAsync(h, w.bounds, (size_t)(pc + 1) * 8, hipMemcpyDeviceToHost, s));
+    BFS_HIP(wait_stream(s));
+    for (int j = 0; j < pc; ++j) {
+      const int64_t lo = h[j], hi = h[j + 1];
+      if (hi <= lo) continue;
+      for (int i = 0; i < pr; ++i) {
+        bfs_svec_t fv{hi - lo, hi - lo, w.fl + lo, f + lo};
+        bfs_svec_t out{0, max_rows, w.oidx, w.oval};
+        const int rc = dcsc_spmspv(shares[(size_t)i * pc + j], &fv, &out, s);
+        if (rc != BFS_OK) return rc;
+        if (out.nnz > 0) {
+          const int fgrid = (int)std::min<int64_t>((out.nnz + ib - 1) / ib, 4096);
+          k2_fold<<<fgrid, ib, 0, s>>>(out.nnz, w.oidx, w.oval, (int64_t)i * R, parent, w.cand,
+                                       w.newbit);
+        }
+      }
+    }
+    k2_count<<<(int)nblk, kApplyBlock, 0, s>>>(w.newbit, nwords, w.blk);
+    k2_scan<<<1, 256, 0, s>>>(w.blk, nblk, w.total);
+    k2_apply<<<(int)nblk, kApplyBlock, 0, s>>>(w.newbit, nwords, w.cand, w.blk, k, parent,
+                                               level, fnext);
+    BFS_HIP(hipGetLastError());
+    BFS_HIP(hipMemcpyAsync(h + pc + 1, w.total, 8, hipMemcpyDeviceToHost, s));
+    BFS_HIP(wait_stream(s));
+    F = h[pc + 1];
+    std::swap(f, fnext);
+    if (k > n + 1) return fail(BFS_ERR_DEVICE, "2D level loop did not terminate");
+  }
+  return BFS_OK;
+}
+
+// ------------------------------------------------------------ no-allocation entry
+// Workspace of bfs_run_2d_noalloc: a file-scope device array, one copy per
+// GPU for the life of the process, shared by every call on that GPU (its
+// contents are whatever the last call left; each call initialises what it
+// reads). Host code reaches it only through the per-device address from
+// hipGetSymbolAddress; the array's name is not a device address there.
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 20;
+constexpr int kNoAllocMaxPc = 256;
+constexpr int64_t kScratchBytes = 26 * ((int64_t)1 << 20);
+static_assert(kScratchBytes >= 4 * kNoAllocMaxN * 4 + 2 * kNoAllocMaxN * 4 +
+                                   kNoAllocMaxN / 8 + 10 * 256 + (kNoAllocMaxPc + 1) * 8 + 4096,
+              "scratch holds the workspace of the largest accepted run");
+__device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The calling thread's current device's copy of `scratch`, looked up once
+// per device with that device current.
+int scratch_for_device(char** out) {
+  int dev = 0;
+  BFS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(BFS_ERR_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return BFS_OK;
+}
+
+}  // namespace
+}  // namespace bfsi
+
+using namespace bfsi;
+
+extern "C" int bfs_run_2d(bfs_graph_t* const* shares, int32_t pr, int32_t pc, int64_t n,
+                          int32_t root, int32_t* parent, int32_t* level, void* hip_stream) {
+  bfs_graph* all[kMaxShares];
+  int64_t max_rows = 1;
+  int rc = check_2d(shares, pr, pc, n, root, parent, level, all, &max_rows);
+  if (rc != BFS_OK) return rc;
   hipStream_t s = (hipStream_t)hip_stream;
   try {
     // the shares' accumulators are used by this run: hold their run locks
+    // (taken in address order)
     std::vector<std::unique_lock<std::mutex>> locks;
-    for (bfs_graph* g : sorted) locks.emplace_back(g->run_mu);
-    Ws2d w;
-    const int64_t nwords = (n + 31) / 32;
-    const int64_t nblk = (nwords + kApplyPerBlock - 1) / kApplyPerBlock;
-    BFS_HIP(hipMalloc(&w.f, (size_t)n * 4));
-    BFS_HIP(hipMalloc(&w.fnext, (size_t)n * 4));
-    BFS_HIP(hipMalloc(&w.fl, (size_t)n * 4));
-    BFS_HIP(hipMalloc(&w.cand, (size_t)n * 4));
-    BFS_HIP(hipMalloc(&w.oidx, (size_t)max_rows * 4));
-    BFS_HIP(hipMalloc(&w.oval, (size_t)max_rows * 4));
-    BFS_HIP(hipMalloc(&w.newbit, (size_t)nwords * 4));
-    BFS_HIP(hipMalloc(&w.bounds, (size_t)(pc + 1) * 8));
-    BFS_HIP(hipMalloc(&w.blk, (size_t)std::max<int64_t>(nblk, 1) * 8));
-    BFS_HIP(hipMalloc(&w.total, 8));
-    BFS_HIP(hipHostMalloc(&w.h, (size_t)(pc + 2) * 8, hipHostMallocDefault));
-    const int ib = 256;
-    const int igrid = (int)std::min<int64_t>((n + ib - 1) / ib, 8192);
-    k2_init<<<igrid, ib, 0, s>>>(n, parent, level, w.cand, w.newbit, nwords, root, w.f);
-    BFS_HIP(hipGetLastError());
-    int64_t F = 1;
-    for (int32_t k = 1; F > 0; ++k) {
-      const int sgrid = (int)std::min<int64_t>((F + ib - 1) / ib, 4096);
-      k2_split<<<sgrid, ib, 0, s>>>(w.f, F, C, pc, w.fl, w.bounds);
-      BFS_HIP(hipMemcpyAsync(w.h, w.bounds, (size_t)(pc + 1) * 8, hipMemcpyDeviceToHost, s));
-      BFS_HIP(hipStreamSynchronize(s));
-      std::vector<int64_t> b(w.h, w.h + pc + 1);
-      for (int j = 0; j < pc; ++j) {
-        const int64_t lo = b[(size_t)j], hi = b[(size_t)j + 1];
-        if (hi <= lo) continue;
-        for (int i = 0; i < pr; ++i) {
-          bfs_svec_t fv{hi - lo, hi - lo, w.fl + lo, w.f + lo};
-          bfs_svec_t out{0, max_rows, w.oidx, w.oval};
-          const int rc = dcsc_spmspv(shares[(size_t)i * pc + j], &fv, &out, s);
-          if (rc != BFS_OK) return rc;
-          if (out.nnz > 0) {
-            const int fgrid = (int)std::min<int64_t>((out.nnz + ib - 1) / ib, 4096);
-            k2_fold<<<fgrid, ib, 0, s>>>(out.nnz, w.oidx, w.oval, (int64_t)i * R, parent,
-                                         w.cand, w.newbit);
-          }
-        }
-      }
-      k2_count<<<(int)nblk, kApplyBlock, 0, s>>>(w.newbit, nwords, w.blk);
-      k2_scan<<<1, 256, 0, s>>>(w.blk, nblk, w.total);
-      k2_apply<<<(int)nblk, kApplyBlock, 0, s>>>(w.newbit, nwords, w.cand, w.blk, k, parent,
-                                                 level, w.fnext);
-      BFS_HIP(hipGetLastError());
-      BFS_HIP(hipMemcpyAsync(w.h + pc + 1, w.total, 8, hipMemcpyDeviceToHost, s));
-      BFS_HIP(hipStreamSynchronize(s));
-      F = w.h[pc + 1];
-      std::swap(w.f, w.fnext);
-      if (k > n + 1) return fail(BFS_ERR_DEVICE, "2D level loop did not terminate");
+    for (int i = 0; i < pr * pc; ++i) locks.emplace_back(all[i]->run_mu);
+    char* ws = nullptr;
+    BFS_HIP(hipMalloc(&ws, (size_t)ws2d_bytes(n, max_rows, pc)));
+    int64_t* h = nullptr;
+    hipError_t e = hipHostMalloc(&h, (size_t)(pc + 2) * 8, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      (void)hipFree(ws);
+      return hip_fail(e, "hipHostMalloc");
     }
-    return BFS_OK;
+    rc = run_2d_core(shares, pr, pc, n, root, parent, level, max_rows,
+                     ws2d_carve(ws, n, max_rows, pc), h, s);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(ws);
+    (void)hipHostFree(h);
+    return rc;
   } catch (...) {
     return fail(BFS_ERR_DEVICE, "exception in bfs_run_2d");
+  }
+}
+
+extern "C" int bfs_run_2d_noalloc(bfs_graph_t* const* shares, int32_t pr, int32_t pc,
+                                  int64_t n, int32_t root, int32_t* parent, int32_t* level,
+                                  void* hip_stream) {
+  bfs_graph* all[kMaxShares];
+  int64_t max_rows = 1;
+  int rc = check_2d(shares, pr, pc, n, root, parent, level, all, &max_rows);
+  if (rc != BFS_OK) return rc;
+  if (n > kNoAllocMaxN)
+    return fail(BFS_ERR_CAPACITY, "bfs_run_2d_noalloc: n above 2^20 (its fixed workspace); "
+                                  "use bfs_run_2d");
+  if (pc > kNoAllocMaxPc)
+    return fail(BFS_ERR_CAPACITY, "bfs_run_2d_noalloc: more than 256 column blocks");
+  if (ws2d_bytes(n, max_rows, pc) > kScratchBytes)
+    return fail(BFS_ERR_CAPACITY, "bfs_run_2d_noalloc: workspace exceeds the fixed scratch");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    char* ws = nullptr;
+    rc = scratch_for_device(&ws);
+    if (rc != BFS_OK) return rc;
+    std::unique_lock<std::mutex> locks[kMaxShares];
+    for (int i = 0; i < pr * pc; ++i) locks[i] = std::unique_lock<std::mutex>(all[i]->run_mu);
+    int64_t h[kNoAllocMaxPc + 2];   // column bounds and frontier size (host stack)
+    return run_2d_core(shares, pr, pc, n, root, parent, level, max_rows,
+                       ws2d_carve(ws, n, max_rows, pc), h, s);
+  } catch (...) {
+    return fail(BFS_ERR_DEVICE, "exception in bfs_run_2d_noalloc");
   }
 }

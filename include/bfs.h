@@ -381,14 +381,14 @@ int bfs_server_destroy(bfs_server_t* s);
 
 /*
  * Autotuner. CSR graph: times BFS from eight seeded roots of positive degree
- * (the median of three passes) and tunes, by coordinate descent from the
+ * (the median of five passes) and tunes, by coordinate descent from the
  * defaults (two sweeps, a knob at a time), the expand grid (2, 4 workgroups
  * per CU), levels per host check (4, 8), mark-level frontier floor (4096,
- * 1024, 16384), pull_alpha (14, 4, 40), mark-level edge floor
- * (claim_threshold: the default, or nnz / 16) and the device level loop's
+ * 1024, 16384, 32), pull_alpha (14, 4, 40), mark-level edge floor
+ * (claim_threshold: the default, nnz / 16 or n / 512) and the device level loop's
  * frontier limit (small_frontier: 8192, 1024, off); a value replaces the
- * current one only when it is more than 3% faster, so repeated tuning keeps
- * the same choice. The result is kept in the handle's options. DCSC share:
+ * current one only when it is more than 5% faster, and again against a fresh
+ * timing of the current one, so repeated tuning keeps the same choice. The result is kept in the handle's options. DCSC share:
  * times both branches of the SpMSpV polyalgorithm (section 4.2: the binned
  * accumulator, or the sort-based merge) on sorted random frontiers of 64 to
  * 8192 entries and sets spmspv_sort_max to the largest size where the sort

@@ -102,11 +102,13 @@ double query_cost(const bfs_graph* g) {
 // Launch shapes and level floors of a CSR graph, chosen by timing BFS from
 // eight seeded roots of positive degree. Coordinate descent from the
 // defaults: each knob in turn tries its values with the others fixed, each
-// setting timed as the median of three passes over the roots, and a value
+// setting timed as the median of five passes over the roots, and a value
 // replaces the current one only when it is faster by more than kTuneMargin,
-// so settings within timing noise of each other keep the earlier one and
+// twice (the second time against a fresh timing of the current setting), so
+// settings within timing noise of each other keep the earlier one and
 // repeated tuning gives the same choice. Two sweeps over the knobs.
-constexpr double kTuneMargin = 0.03;
+constexpr double kTuneMargin = 0.05;
+constexpr int kTunePasses = 5;
 
 int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   const int64_t n = g->csr.n;
@@ -136,6 +138,9 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   // adjacencies (graphs without hubs, where a push level's resolve scans far
   // for a small frontier's vertices)
   const int ct16 = (int)std::min<int64_t>(g->csr.nnz / 16, INT32_MAX);
+  // or n / 512: a frontier of a few hubs (R-MAT's second level) pushed
+  // without a claim per edge
+  const int ct_low = (int)std::max<int64_t>(g->csr.n / 512, 4096);
   struct Knob {
     int32_t bfs_options_t::*field;
     std::vector<int32_t> values;   // values[0] is the default
@@ -143,9 +148,9 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   const std::vector<Knob> knobs = {
       {&bfs_options_t::grid_blocks, {cus * 2, cus * 4}},
       {&bfs_options_t::batch_levels, {4, 8}},
-      {&bfs_options_t::claim_min_frontier, {4096, 1024, 16384}},
+      {&bfs_options_t::claim_min_frontier, {4096, 1024, 16384, 32}},
       {&bfs_options_t::pull_alpha, {14, 4, 40}},
-      {&bfs_options_t::claim_threshold, {0, ct16}},
+      {&bfs_options_t::claim_threshold, {0, ct16, ct_low}},
       {&bfs_options_t::small_frontier, {8192, 1024, -1}},
   };
   bfs_options_t cur = saved;
@@ -155,8 +160,8 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
     g->opt = o;
     int r = csr_run(g, cand[0], parent, level, nullptr, true);   // warm
     if (r != BFS_OK) return r;
-    double t[3];
-    for (int pass = 0; pass < 3; ++pass) {
+    double t[kTunePasses];
+    for (int pass = 0; pass < kTunePasses; ++pass) {
       const auto t0 = std::chrono::steady_clock::now();
       for (int32_t root : cand) {
         r = csr_run(g, root, parent, level, nullptr, true);
@@ -164,8 +169,8 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
       }
       t[pass] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
-    std::sort(t, t + 3);
-    *out = t[1];
+    std::sort(t, t + kTunePasses);
+    *out = t[kTunePasses / 2];
     return BFS_OK;
   };
   double best = 0.0;
@@ -180,8 +185,18 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
         rc = measure(o, &t);
         if (rc != BFS_OK) break;
         if (t < best * (1.0 - kTuneMargin)) {
-          best = t;
-          cur = o;
+          // confirm against a fresh timing of the current setting, so one
+          // slow measurement of it does not decide the choice
+          double tc = 0.0, to = 0.0;
+          rc = measure(cur, &tc);
+          if (rc == BFS_OK) rc = measure(o, &to);
+          if (rc != BFS_OK) break;
+          if (to < tc * (1.0 - kTuneMargin)) {
+            best = to;
+            cur = o;
+          } else {
+            best = tc;
+          }
         }
       }
       if (rc != BFS_OK) break;

@@ -99,10 +99,10 @@ constexpr int kMaxBins = 8192;          // 2^31 rows
 constexpr int kBinBlock = 1024;
 constexpr int kStage = 4096;            // products staged in LDS between bin rounds
 constexpr int kStagePer = kStage / kBinBlock;
-// frontier entries looked up together per thread: 8 while the per-bin
-// counters (8 B per bin, dynamic LDS) leave room, else 2
-constexpr int kWideEntries = 8, kNarrowEntries = 2;
-constexpr int kWideMaxBins = 4096;
+// frontier entries looked up together per thread: 2 (two workgroups per CU
+// fit, which hides more latency than more entries per thread in one), or 1
+// for small frontiers so that more CUs take part
+constexpr int kNarrowEntries = 2, kSingleEntries = 1;
 constexpr int kReduceBlock = 1024;
 constexpr int kValCap = 16384;          // rows of one bin reduced in LDS; more use the SPA
 // chained-scan flag word: epoch (30 bits) | status (2 bits) | count (32 bits)
@@ -727,14 +727,20 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   // the binning kernel's per-bin counters live in dynamic LDS (8 B per bin)
   (void)hipFuncSetAttribute((const void*)k_spmspv_bin<kNarrowEntries>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxBins * 8);
-  (void)hipFuncSetAttribute((const void*)k_spmspv_bin<kWideEntries>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kWideMaxBins * 8);
+  (void)hipFuncSetAttribute((const void*)k_spmspv_bin<kSingleEntries>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxBins * 8);
   (void)hipGetLastError();
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) !=
           hipSuccess || cus <= 0)
     cus = 256;
-  d.grid_bin = cus;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_spmspv_bin<kNarrowEntries>,
+                                                   kBinBlock, (size_t)d.nbins * 8) !=
+          hipSuccess || occ <= 0)
+    occ = 1;
+  (void)hipGetLastError();
+  d.grid_bin = cus * occ;   // co-resident workgroups of the binning kernel
   d.epoch = 1;
   g->device_bytes += d.naux * 4 + (int64_t)std::max(d.nrows, 1) * 4 +
                      (int64_t)(d.nbins + 1) * 8 + (int64_t)d.nbins * 12 + 8 +
@@ -816,15 +822,12 @@ int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t 
   ba.counters = d.counters;
   ba.epoch = d.epoch;
   const size_t dyn = (size_t)d.nbins * 8;
-  if (d.nbins <= kWideMaxBins) {
-    const int64_t nsub = (f->nnz + kBinBlock * kWideEntries - 1) / (kBinBlock * kWideEntries);
-    k_spmspv_bin<kWideEntries>
-        <<<(int)std::min<int64_t>(nsub, d.grid_bin), kBinBlock, dyn, s>>>(ba);
+  auto nsub = [&](int ept) { return (f->nnz + kBinBlock * ept - 1) / (kBinBlock * ept); };
+  if (nsub(kNarrowEntries) >= d.grid_bin) {
+    k_spmspv_bin<kNarrowEntries><<<d.grid_bin, kBinBlock, dyn, s>>>(ba);
   } else {
-    const int64_t nsub =
-        (f->nnz + kBinBlock * kNarrowEntries - 1) / (kBinBlock * kNarrowEntries);
-    k_spmspv_bin<kNarrowEntries>
-        <<<(int)std::min<int64_t>(nsub, d.grid_bin), kBinBlock, dyn, s>>>(ba);
+    k_spmspv_bin<kSingleEntries>
+        <<<(int)std::min<int64_t>(nsub(kSingleEntries), d.grid_bin), kBinBlock, dyn, s>>>(ba);
   }
   ReduceArgs ra;
   ra.nbins = d.nbins;

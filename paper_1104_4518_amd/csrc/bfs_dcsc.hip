@@ -62,6 +62,15 @@ __global__ void k_build_aux(const int32_t* __restrict__ jc, int32_t nzc, int shi
   }
 }
 
+// jcp[p] = (jc[p], cp[p]) for p < nzc, jcp[nzc] = (INT32_MAX, nnz): a column's
+// id and both ends of its row list sit in adjacent words
+__global__ void k_build_jcp(const int32_t* __restrict__ jc, const int32_t* __restrict__ cp,
+                            int32_t nzc, int2* __restrict__ jcp) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p <= nzc; p += stride)
+    jcp[p] = make_int2(p < nzc ? jc[p] : INT32_MAX, cp[p]);
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -103,6 +112,7 @@ constexpr int kStagePer = kStage / kBinBlock;
 // fit, which hides more latency than more entries per thread in one), or 1
 // for small frontiers so that more CUs take part
 constexpr int kNarrowEntries = 2, kSingleEntries = 1;
+constexpr int kProbe = 4;               // stored columns of a bucket read at once
 constexpr int kReduceBlock = 1024;
 constexpr int kValCap = 16384;          // rows of one bin reduced in LDS; more use the SPA
 // chained-scan flag word: epoch (30 bits) | status (2 bits) | count (32 bits)
@@ -132,17 +142,18 @@ struct BinArgs {
 // step), then the sub-chunk's products are expanded edge-balanced into the
 // LDS stage, which is binned whenever it fills.
 template <int EPT>
-__global__ __launch_bounds__(kBinBlock) void k_spmspv_bin(BinArgs a) {
+__global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmspv_bin(BinArgs a) {
   constexpr int WAVES = kBinBlock / 64;
   constexpr int SUB = kBinBlock * EPT;
   __shared__ int32_t s_pre[SUB];            // product prefix of the sub-chunk's entries
   __shared__ int32_t s_q0[SUB];             // first stored entry of the entry's column
+  __shared__ uint32_t s_fv[SUB];            // the entries' values (order-preserving key)
   __shared__ int32_t s_row[kStage];         // staged products
   __shared__ uint32_t s_kst[kStage];
   __shared__ int s_w[WAVES];
-  extern __shared__ int32_t s_dyn[];
-  int32_t* s_hist = s_dyn;                  // products per bin this round (kept zero)
-  int32_t* s_base = s_dyn + a.nbins;        // reserved slot of the round's first product
+  extern __shared__ long long s_dyn[];
+  long long* s_base = s_dyn;                // pair slot of the round's first product, or -1
+  int32_t* s_hist = reinterpret_cast<int32_t*>(s_dyn + a.nbins);   // products per bin (kept zero)
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wid = tid >> 6;
@@ -164,7 +175,10 @@ __global__ __launch_bounds__(kBinBlock) void k_spmspv_bin(BinArgs a) {
     for (int b = tid; b < a.nbins; b += kBinBlock) {
       const int h = s_hist[b];
       if (h) {
-        s_base[b] = atomicAdd(&a.cursor[b], h);
+        // a valid frontier never exceeds a bin's slice (each stored entry
+        // gives at most one product); a repeated column could
+        const int64_t pos = a.bin_start[b] + atomicAdd(&a.cursor[b], h);
+        s_base[b] = pos + h <= a.bin_start[b + 1] ? pos : -1;
         s_hist[b] = 0;
       }
     }
@@ -174,13 +188,9 @@ __global__ __launch_bounds__(kBinBlock) void k_spmspv_bin(BinArgs a) {
       const int j = tid + i * kBinBlock;
       if (j < S) {
         const int32_t row = s_row[j];
-        const int b = row >> kBinShift;
-        const int64_t st = a.bin_start[b];
-        const int64_t pos = st + (int64_t)s_base[b] + rk[i];
-        // a valid frontier never exceeds a bin's slice (each stored entry
-        // gives at most one product); a repeated column could
-        if (pos < a.bin_start[b + 1])
-          a.pairs[pos] = ((unsigned long long)(uint32_t)(row & (kBinRows - 1)) << 32) | s_kst[j];
+        const long long base = s_base[row >> kBinShift];
+        if (base >= 0)
+          a.pairs[base + rk[i]] = ((unsigned long long)(uint32_t)(row & (kBinRows - 1)) << 32) | s_kst[j];
         else
           bad = true;
       }
@@ -189,16 +199,35 @@ __global__ __launch_bounds__(kBinBlock) void k_spmspv_bin(BinArgs a) {
   };
 
   const int64_t nsub = (a.fnnz + SUB - 1) / SUB;
+  // the frontier entries of a sub-chunk (thread t owns entries t*EPT ..
+  // t*EPT + EPT - 1) and the entry before them; the next sub-chunk's are
+  // loaded while the current one is expanded
+  int32_t nk[EPT], nv[EPT], nprev = -1;
+  auto load_entries = [&](int64_t c) {
+    const int64_t c0 = c * SUB;
+    const int nE = c < nsub ? (int)min((int64_t)SUB, a.fnnz - c0) : 0;
+    const int64_t i0 = c0 + (int64_t)tid * EPT;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const bool in = tid * EPT + j < nE;
+      nk[j] = in ? a.fidx[i0 + j] : -1;
+      nv[j] = in && a.fval ? a.fval[i0 + j] : nk[j];
+    }
+    nprev = (tid * EPT < nE && i0 > 0) ? a.fidx[i0 - 1] : -1;
+  };
+  load_entries(blockIdx.x);
   for (int64_t c = blockIdx.x; c < nsub; c += gridDim.x) {
     const int64_t c0 = c * SUB;
     const int nE = (int)min((int64_t)SUB, a.fnnz - c0);
-    // lookup: thread t owns entries t*EPT .. t*EPT + EPT - 1
-    int32_t kk[EPT], lo[EPT], hi[EPT], bend[EPT];
+    // lookup
+    int32_t kk[EPT], kv[EPT], lo[EPT], hi[EPT], bend[EPT];
     {
-      const int64_t i0 = c0 + (int64_t)tid * EPT;
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) kk[j] = tid * EPT + j < nE ? a.fidx[i0 + j] : -1;
-      const int32_t prev = (tid * EPT < nE && i0 > 0) ? a.fidx[i0 - 1] : -1;
+      for (int j = 0; j < EPT; ++j) {
+        kk[j] = nk[j];
+        kv[j] = nv[j];
+      }
+      const int32_t prev = nprev;
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
         lo[j] = hi[j] = bend[j] = 0;
@@ -214,6 +243,28 @@ __global__ __launch_bounds__(kBinBlock) void k_spmspv_bin(BinArgs a) {
         hi[j] = bend[j] = a.aux[bk + 1];
       }
     }
+    // column positions: with one entry per thread (small frontiers, whose
+    // lookups are scattered) the bucket's first kProbe stored columns are
+    // read together, which decides most lookups (buckets hold about four)
+    // in one step; otherwise, and past them, a binary search in the bucket
+    int32_t q0[EPT], len[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) q0[j] = -1;
+    if constexpr (EPT == 1) {
+      int32_t w[kProbe];
+#pragma unroll
+      for (int i = 0; i < kProbe; ++i) w[i] = lo[0] + i < hi[0] ? a.jc[lo[0] + i] : INT32_MAX;
+      int c = 0;
+#pragma unroll
+      for (int i = 0; i < kProbe; ++i) c += w[i] < kk[0];
+      int32_t at = INT32_MAX;
+#pragma unroll
+      for (int i = kProbe - 1; i >= 0; --i)
+        if (i == c) at = w[i];
+      if (kk[0] >= 0 && c < kProbe && at == kk[0]) q0[0] = lo[0] + c;
+      if (kk[0] >= 0 && c == kProbe && lo[0] + kProbe < hi[0]) lo[0] += kProbe;
+      else lo[0] = hi[0];
+    }
     for (;;) {
       bool any = false;
 #pragma unroll
@@ -225,20 +276,19 @@ __global__ __launch_bounds__(kBinBlock) void k_spmspv_bin(BinArgs a) {
         }
       if (!any) break;
     }
-    int32_t q0[EPT], len[EPT];
-    int mine = 0;
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const bool found = kk[j] >= 0 && lo[j] < bend[j] && a.jc[lo[j]] == kk[j];
-      q0[j] = found ? lo[j] : -1;
-    }
+    for (int j = 0; j < EPT; ++j)
+      if (q0[j] < 0 && kk[j] >= 0 && lo[j] < bend[j] && a.jc[lo[j]] == kk[j]) q0[j] = lo[j];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       const int32_t p = q0[j];
       q0[j] = p >= 0 ? a.cp[p] : 0;
       len[j] = p >= 0 ? a.cp[p + 1] - q0[j] : 0;
-      mine += len[j];
     }
+    int mine = 0;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) mine += len[j];
+    load_entries(c + gridDim.x);
     // exclusive product prefix over the sub-chunk's entries (entry order)
     const int incl = (int)wave_incl_scan((long long)mine);
     if (lane == 63) s_w[wid] = incl;
@@ -257,14 +307,14 @@ __global__ __launch_bounds__(kBinBlock) void k_spmspv_bin(BinArgs a) {
         if (e < nE) {
           s_pre[e] = ex;
           s_q0[e] = q0[j];
+          s_fv[e] = (uint32_t)kv[j] ^ 0x80000000u;
         }
         ex += len[j];
       }
     }
     __syncthreads();
     // expand: product jj belongs to the last entry whose prefix is <= jj
-    // (entries without products share their successor's prefix); its value
-    // is read again from the frontier (a cached line)
+    // (entries without products share their successor's prefix)
     for (int done = 0; done < P;) {
       const int take = min(P - done, kStage - staged);
       for (int j = tid; j < take; j += kBinBlock) {
@@ -274,9 +324,8 @@ __global__ __launch_bounds__(kBinBlock) void k_spmspv_bin(BinArgs a) {
           const int mid = (l + h + 1) >> 1;
           if (s_pre[mid] <= jj) l = mid; else h = mid - 1;
         }
-        const int64_t i = c0 + l;
         s_row[staged + j] = a.ir[s_q0[l] + (jj - s_pre[l])];
-        s_kst[staged + j] = (uint32_t)(a.fval ? a.fval[i] : a.fidx[i]) ^ 0x80000000u;
+        s_kst[staged + j] = s_fv[l];
       }
       staged += take;
       done += take;
@@ -300,6 +349,7 @@ struct ReduceArgs {
   int32_t* ticket;          // [0] bin ticket, [1] finished workgroups
   uint32_t* spa_val;        // nrows, all ones between calls (bins over kValCap rows)
   unsigned long long* counters;
+  unsigned long long* host;  // pinned host words the results are written to
   uint32_t epoch;
   int64_t capacity;
   int32_t* out_idx;
@@ -476,10 +526,18 @@ __global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
   if (tid == 0) {
     a.cursor[b] = 0;   // the bin's slice is empty for the next call
     if (b == a.nbins - 1) a.counters[0] = err ? 0ull : (unsigned long long)(s_excl + U);
-    // the last workgroup to finish rewinds the tickets
+    __threadfence();
+    // the last workgroup to finish rewinds the tickets and hands the call's
+    // results to the host: output count, error epochs, and the epoch itself
+    // as the mark that the call completed
     if (atomicAdd(&a.ticket[1], 1) == a.nbins - 1) {
+      __threadfence();
       a.ticket[0] = 0;
       a.ticket[1] = 0;
+      a.host[0] = __hip_atomic_load(&a.counters[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a.host[1] = __hip_atomic_load(&a.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a.host[3] = __hip_atomic_load(&a.counters[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a.host[2] = a.epoch;
     }
   }
 }
@@ -694,6 +752,8 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   d.naux = ((int64_t)std::max(d.ncols, 1) >> shift) + 2;
   BFS_HIP(hipMalloc(&d.aux, (size_t)d.naux * 4));
   k_build_aux<<<1024, 256, 0, s>>>(d.jc, d.nzc, shift, d.naux, d.aux);
+  BFS_HIP(hipMalloc(&d.jcp, ((size_t)d.nzc + 1) * sizeof(int2)));
+  k_build_jcp<<<1024, 256, 0, s>>>(d.jc, d.cp, d.nzc, d.jcp);
   // row bins: each owns a slice of the pair buffer as long as its stored entries
   d.nbins = (int32_t)(((int64_t)std::max(d.nrows, 1) + kBinRows - 1) >> kBinShift);
   BFS_HIP(hipMalloc(&d.bin_start, (size_t)(d.nbins + 1) * 8));
@@ -723,12 +783,14 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   BFS_HIP(hipMalloc(&d.counters, 4 * sizeof(unsigned long long)));
   BFS_HIP(hipMemsetAsync(d.counters, 0, 4 * sizeof(unsigned long long), s));
   BFS_HIP(hipHostMalloc(&d.h_counters, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+  d.h_counters[2] = 0ull;
+  BFS_HIP(hipHostGetDevicePointer((void**)&d.h_counters_dev, d.h_counters, 0));
   BFS_HIP(hipStreamSynchronize(s));
-  // the binning kernel's per-bin counters live in dynamic LDS (8 B per bin)
+  // the binning kernel's per-bin counters live in dynamic LDS (12 B per bin)
   (void)hipFuncSetAttribute((const void*)k_spmspv_bin<kNarrowEntries>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxBins * 8);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxBins * 12);
   (void)hipFuncSetAttribute((const void*)k_spmspv_bin<kSingleEntries>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxBins * 8);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxBins * 12);
   (void)hipGetLastError();
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) !=
@@ -736,13 +798,13 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
     cus = 256;
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_spmspv_bin<kNarrowEntries>,
-                                                   kBinBlock, (size_t)d.nbins * 8) !=
+                                                   kBinBlock, (size_t)d.nbins * 12) !=
           hipSuccess || occ <= 0)
     occ = 1;
   (void)hipGetLastError();
   d.grid_bin = cus * occ;   // co-resident workgroups of the binning kernel
   d.epoch = 1;
-  g->device_bytes += d.naux * 4 + (int64_t)std::max(d.nrows, 1) * 4 +
+  g->device_bytes += d.naux * 4 + ((int64_t)d.nzc + 1) * 8 + (int64_t)std::max(d.nrows, 1) * 4 +
                      (int64_t)(d.nbins + 1) * 8 + (int64_t)d.nbins * 12 + 8 +
                      std::max<int64_t>(d.nnz, 1) * 8 + 32;
   return BFS_OK;
@@ -752,6 +814,7 @@ void dcsc_free(bfs_graph* g) {
   DcscDev& d = g->dcsc;
   (void)hipFree(d.jc);
   (void)hipFree(d.cp);
+  (void)hipFree(d.jcp);
   (void)hipFree(d.ir);
   (void)hipFree(d.aux);
   (void)hipFree(d.spa_val);
@@ -821,7 +884,7 @@ int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t 
   ba.pairs = d.pairs;
   ba.counters = d.counters;
   ba.epoch = d.epoch;
-  const size_t dyn = (size_t)d.nbins * 8;
+  const size_t dyn = (size_t)d.nbins * 12;
   auto nsub = [&](int ept) { return (f->nnz + kBinBlock * ept - 1) / (kBinBlock * ept); };
   if (nsub(kNarrowEntries) >= d.grid_bin) {
     k_spmspv_bin<kNarrowEntries><<<d.grid_bin, kBinBlock, dyn, s>>>(ba);
@@ -838,22 +901,24 @@ int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t 
   ra.ticket = d.ticket;
   ra.spa_val = d.spa_val;
   ra.counters = d.counters;
+  ra.host = d.h_counters_dev;
   ra.epoch = d.epoch;
   ra.capacity = out->capacity;
   ra.out_idx = out->idx;
   ra.out_val = out->val;
   k_spmspv_reduce<<<d.nbins, kReduceBlock, 0, s>>>(ra);
   BFS_HIP(hipGetLastError());
-  BFS_HIP(hipMemcpyAsync(d.h_counters, d.counters, 4 * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, s));
   BFS_HIP(wait_stream(s));
-  if (d.h_counters[1] == d.epoch) {
+  const volatile unsigned long long* h = d.h_counters;
+  if (h[2] != d.epoch)
+    return fail(BFS_ERR_DEVICE, "spmspv: the reduction over the row bins did not complete");
+  if (h[1] == d.epoch) {
     out->nnz = 0;
     return fail(BFS_ERR_ARG, "frontier indices must be strictly ascending and in [0, ncols)");
   }
-  if (d.h_counters[3] == d.epoch)
+  if (h[3] == d.epoch)
     return fail(BFS_ERR_DEVICE, "spmspv: chained scan over the row bins did not complete");
-  const int64_t cnt = (int64_t)d.h_counters[0];
+  const int64_t cnt = (int64_t)h[0];
   out->nnz = cnt;
   if (cnt > out->capacity) return fail(BFS_ERR_CAPACITY, "output capacity too small");
   return BFS_OK;

@@ -153,6 +153,7 @@ struct DcscDev {
   int32_t* ir = nullptr;
   int aux_shift = 0;             // column bucket width = 2^aux_shift
   int64_t naux = 0;
+  int2* jcp = nullptr;           // (jc[p], cp[p]) pairs, nzc + 1 of them
   int32_t* aux = nullptr;        // aux[b] = first p with jc[p] >= b << aux_shift
   // binned product: rows in bins of 2^18, bin b's products in
   // pairs[bin_start[b] .. bin_start[b + 1]) ((row in bin) << 32 | value)
@@ -168,7 +169,11 @@ struct DcscDev {
   // [0] out count, [1] frontier error (epoch), [2] sort path: product too
   // large, [3] chained-scan failure (epoch)
   unsigned long long* counters = nullptr;
-  unsigned long long* h_counters = nullptr;  // pinned host copy
+  // pinned host words: the sort path copies counters [0..2] there; the
+  // binned path's reduction writes [0] count, [1] and [3] the error epochs,
+  // [2] the epoch of the call it completed (device address h_counters_dev)
+  unsigned long long* h_counters = nullptr;
+  unsigned long long* h_counters_dev = nullptr;
 };
 
 }  // namespace bfsi

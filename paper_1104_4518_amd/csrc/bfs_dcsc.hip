@@ -62,15 +62,6 @@ __global__ void k_build_aux(const int32_t* __restrict__ jc, int32_t nzc, int shi
   }
 }
 
-// jcp[p] = (jc[p], cp[p]) for p < nzc, jcp[nzc] = (INT32_MAX, nnz): a column's
-// id and both ends of its row list sit in adjacent words
-__global__ void k_build_jcp(const int32_t* __restrict__ jc, const int32_t* __restrict__ cp,
-                            int32_t nzc, int2* __restrict__ jcp) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p <= nzc; p += stride)
-    jcp[p] = make_int2(p < nzc ? jc[p] : INT32_MAX, cp[p]);
-}
-
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -752,8 +743,6 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   d.naux = ((int64_t)std::max(d.ncols, 1) >> shift) + 2;
   BFS_HIP(hipMalloc(&d.aux, (size_t)d.naux * 4));
   k_build_aux<<<1024, 256, 0, s>>>(d.jc, d.nzc, shift, d.naux, d.aux);
-  BFS_HIP(hipMalloc(&d.jcp, ((size_t)d.nzc + 1) * sizeof(int2)));
-  k_build_jcp<<<1024, 256, 0, s>>>(d.jc, d.cp, d.nzc, d.jcp);
   // row bins: each owns a slice of the pair buffer as long as its stored entries
   d.nbins = (int32_t)(((int64_t)std::max(d.nrows, 1) + kBinRows - 1) >> kBinShift);
   BFS_HIP(hipMalloc(&d.bin_start, (size_t)(d.nbins + 1) * 8));
@@ -804,7 +793,7 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   (void)hipGetLastError();
   d.grid_bin = cus * occ;   // co-resident workgroups of the binning kernel
   d.epoch = 1;
-  g->device_bytes += d.naux * 4 + ((int64_t)d.nzc + 1) * 8 + (int64_t)std::max(d.nrows, 1) * 4 +
+  g->device_bytes += d.naux * 4 + (int64_t)std::max(d.nrows, 1) * 4 +
                      (int64_t)(d.nbins + 1) * 8 + (int64_t)d.nbins * 12 + 8 +
                      std::max<int64_t>(d.nnz, 1) * 8 + 32;
   return BFS_OK;
@@ -814,7 +803,6 @@ void dcsc_free(bfs_graph* g) {
   DcscDev& d = g->dcsc;
   (void)hipFree(d.jc);
   (void)hipFree(d.cp);
-  (void)hipFree(d.jcp);
   (void)hipFree(d.ir);
   (void)hipFree(d.aux);
   (void)hipFree(d.spa_val);

@@ -153,7 +153,6 @@ struct DcscDev {
   int32_t* ir = nullptr;
   int aux_shift = 0;             // column bucket width = 2^aux_shift
   int64_t naux = 0;
-  int2* jcp = nullptr;           // (jc[p], cp[p]) pairs, nzc + 1 of them
   int32_t* aux = nullptr;        // aux[b] = first p with jc[p] >= b << aux_shift
   // binned product: rows in bins of 2^18, bin b's products in
   // pairs[bin_start[b] .. bin_start[b + 1]) ((row in bin) << 32 | value)

@@ -434,9 +434,66 @@ def bfs_workload(name, args, torch, graphgen, B, np, cpu: bool, steps: int, warm
     if cpu:
         log(f"{name}: cpu baseline")
         cb = cpu_baseline(g, [roots[i] for i in giant], args.cpu_budget)
+    if args.upper_storage and name == args.workload:
+        res["upper_storage"] = upper_storage(g, G, roots, giant, value, all_ms, torch, graphgen,
+                                             B, np, min(steps, 3))
     G.destroy()
     del g
     return res, cb
+
+
+def upper_storage(g, G, roots, giant, gteps_full, ms_full, torch, graphgen, B, np, steps):
+    """The same searches on symmetric storage (each undirected edge once, in
+    the row of its smaller endpoint): device bytes and time against the full
+    CSR, and the outputs of a few roots compared with the full CSR's."""
+    t0 = time.time()
+    u = graphgen.upper_csr(g)
+    log(f"{g.name}: upper-triangle copy ({u.nnz} adjacencies) in {time.time() - t0:.1f}s")
+    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    level = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    ref = []
+    for r in roots[:2]:
+        G.run(r, parent, level)
+        ref.append((parent.clone(), level.clone()))
+    full_bytes = G.info()[2]
+    G.destroy()   # freed first: the two copies never share the device
+    Gu = B.Graph.from_csr(u.n, u.off, u.col, trusted=True, upper=True)
+    Gu.tune()
+    Gu.set_options(profile=-1)
+    same = True
+    for (rp, rl), r in zip(ref, roots[:2]):
+        Gu.run(r, parent, level)
+        same &= bool(torch.equal(parent, rp)) and bool(torch.equal(level, rl))
+    del ref
+    for r in roots:   # warm-up pass
+        Gu.run(r, parent, level)
+    nr = len(roots)
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(nr)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for s in range(steps):
+        for i, r in enumerate(roots):
+            ev[s][i][0].record()
+            Gu.run(r, parent, level)
+            ev[s][i][1].record()
+    torch.cuda.synchronize()
+    ms = [[ev[s][i][0].elapsed_time(ev[s][i][1]) for i in range(nr)] for s in range(steps)]
+    Gu.run(roots[giant[0]], parent, level)
+    edges = Gu.last_stats().edges_traversed
+    vals = [edges // 2 / (ms[s][i] * 1e-3) / 1e9 for s in range(steps) for i in giant]
+    up_bytes = Gu.info()[2]
+    Gu.destroy()
+    gteps = harmonic(vals)
+    all_ms = [x for row in ms for x in row]
+    log(f"{g.name}: upper-triangle storage {up_bytes / 1e9:.2f} GB on device "
+        f"(full CSR {full_bytes / 1e9:.2f} GB), {gteps:.2f} GTEPS (full {gteps_full:.2f}), "
+        f"p50 {pct(all_ms, 50):.3f} ms, outputs equal to the full CSR's: {same}")
+    return {"adjacencies_stored": int(u.nnz), "adjacencies_full": int(g.nnz),
+            "device_bytes_upper": int(up_bytes), "device_bytes_full": int(full_bytes),
+            "gteps_upper": round(gteps, 3), "gteps_full": round(gteps_full, 3),
+            "ms_per_bfs_p50_upper": round(pct(all_ms, 50), 4),
+            "ms_per_bfs_p50_full": round(pct(ms_full, 50), 4),
+            "passes": steps, "outputs_equal_full_csr": same}
 
 
 # ------------------------------------------------------------------ SpMSpV leg
@@ -684,6 +741,8 @@ def main() -> int:
                          "(e.g. the tuned_options of an earlier line), for profiled runs")
     ap.add_argument("--spmspv-densities", default="0.0001,0.001,0.01,0.1",
                     help="frontier densities of the SpMSpV leg")
+    ap.add_argument("--no-upper-storage", dest="upper_storage", action="store_false",
+                    help="skip the headline graph's run on symmetric (upper-triangle) storage")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (3 times), to scale HBM counters")
     args = ap.parse_args()

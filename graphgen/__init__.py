@@ -310,12 +310,22 @@ def upper_csr(g: CSR) -> CSR:
     once, in the row of its smaller endpoint, i.e. the entries v > u of every
     row u, kept in ascending order."""
     n = g.n
-    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.off))
-    keep = g.col.astype(np.int64) > src
-    cnt = np.bincount(src[keep], minlength=n)
+    goff = np.asarray(g.off, dtype=np.int64)
+    cnt = np.zeros(n, np.int64)
+    parts = []
+    step = 1 << 21   # rows per chunk, so that scale-26 graphs fit in host memory
+    for r0 in range(0, n, step):
+        r1 = min(n, r0 + step)
+        a, b = int(goff[r0]), int(goff[r1])
+        src = np.repeat(np.arange(r0, r1, dtype=np.int32), np.diff(goff[r0:r1 + 1]))
+        cols = g.col[a:b]
+        keep = cols > src
+        cnt[r0:r1] = np.bincount(src[keep] - r0, minlength=r1 - r0)
+        parts.append(cols[keep])
     off = np.zeros(n + 1, np.int64)
     np.cumsum(cnt, out=off[1:])
-    return CSR(n, off, np.ascontiguousarray(g.col[keep]), name=g.name + "_upper")
+    col = np.concatenate(parts) if parts else np.zeros(0, np.int32)
+    return CSR(n, off, np.ascontiguousarray(col, dtype=np.int32), name=g.name + "_upper")
 
 
 def csr_to_2d(g: CSR, pr: int, pc: int):

@@ -496,6 +496,33 @@ def upper_storage(g, G, roots, giant, gteps_full, ms_full, torch, graphgen, B, n
             "passes": steps, "outputs_equal_full_csr": same}
 
 
+def bfs_floor(torch, graphgen, B, np):
+    """The fixed cost of one search: BFS on a single edge (2 vertices), with
+    the default options, timed like the workloads (an event pair around each
+    call)."""
+    g = graphgen.from_edges(2, [(0, 1)])
+    G = B.Graph.from_csr(g.n, g.off, g.col, trusted=True, symmetric=True)
+    G.set_options(profile=-1)
+    parent = torch.empty(2, dtype=torch.int32, device="cuda")
+    level = torch.empty(2, dtype=torch.int32, device="cuda")
+    ms = []
+    for rep in range(41):
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        G.run(rep & 1, parent, level)
+        e.record()
+        torch.cuda.synchronize()
+        if rep:
+            ms.append(s.elapsed_time(e))
+    opt = G.get_options()
+    G.destroy()
+    us = pct(ms, 50) * 1e3
+    log(f"bfs floor (one edge): p50 {us:.1f} us per search")
+    return {"graph": "one edge, 2 vertices", "us_per_bfs_p50": round(us, 1),
+            "batch_levels": opt.batch_levels}
+
+
 # ------------------------------------------------------------------ SpMSpV leg
 def spmspv_leg(args, torch, graphgen, B, np):
     t0 = time.time()
@@ -790,6 +817,8 @@ def main() -> int:
         for k in ("roofline", "level_kernels", "bfs_roofline_frac", "bfs_examined_frac",
                   "ms_per_bfs_p50", "pass_gteps", "levels_p50", "pull_levels_p50"):
             out[k] = res[k]
+        if "upper_storage" in res:
+            out["upper_storage"] = res["upper_storage"]
         if cpu is not None:
             out["cpu_baseline"] = cpu
         extra = {}
@@ -805,6 +834,7 @@ def main() -> int:
                            "roofline": r2["roofline"], "level_kernels": r2["level_kernels"],
                            "pass_gteps": r2["pass_gteps"], "config": cfg}
         out["workloads"] = extra
+        out["bfs_floor"] = bfs_floor(torch, graphgen, B, np)
     if "spmspv" in legs:
         out["spmspv"] = spmspv_leg(args, torch, graphgen, B, np)
     if "mix" in legs:

@@ -150,7 +150,9 @@ typedef struct bfs_options {
   int32_t claim_threshold; /* frontier edges from which a level uses mark-and-resolve
                               (0 = keep; default max(n / 64, 4096)) */
   int32_t claim_min_frontier; /* frontier vertices from which a level uses mark-and-resolve
-                                 (0 = keep; default n / 1024 clamped to [1024, 4096]) */
+                                 (0 = keep; default n / 1024 clamped to [1024, 4096]); a
+                                 frontier whose adjacencies times pull_alpha reach nnz
+                                 pulls whatever its vertex count */
   int32_t cold_probe;   /* mark-and-resolve expands, targets beyond the LDS-resident hot
                            prefix of the visited bitmap: 1 = read the touch-mark byte;
                            2 = read the visited word first, the byte only when unvisited;
@@ -381,13 +383,14 @@ int bfs_server_destroy(bfs_server_t* s);
 
 /*
  * Autotuner. CSR graph: times BFS from eight seeded roots of positive degree
- * (the median of five passes) and tunes, by coordinate descent from the
+ * (each root's fastest of five runs, summed) and tunes, by coordinate descent from the
  * defaults (two sweeps, a knob at a time), the expand grid (2, 4 workgroups
- * per CU), levels per host check (4, 8), mark-level frontier floor (4096,
- * 1024, 16384, 32), pull_alpha (14, 4, 40), mark-level edge floor
- * (claim_threshold: the default, nnz / 16 or n / 512) and the device level loop's
- * frontier limit (small_frontier: 8192, 1024, off); a value replaces the
- * current one only when it is more than 5% faster, and again against a fresh
+ * per CU), levels per host check (4, 8), the two mark-level floors together
+ * (claim_min_frontier, claim_threshold: (4096, default), (1024, default),
+ * (16384, default), (32, n / 512), (1024, n / 512), (4096, nnz / 16)),
+ * pull_alpha (14, 4, 40) and the device level loop's frontier limit
+ * (small_frontier: 8192, 1024, off); a value replaces the
+ * current one only when it is more than 8% faster, and again against a fresh
  * timing of the current one, so repeated tuning keeps the same choice. The result is kept in the handle's options. DCSC share:
  * times both branches of the SpMSpV polyalgorithm (section 4.2: the binned
  * accumulator, or the sort-based merge) on sorted random frontiers of 64 to

@@ -14,6 +14,7 @@
 #include <sstream>
 #include <unordered_set>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "bfs_multi.h"
@@ -102,12 +103,13 @@ double query_cost(const bfs_graph* g) {
 // Launch shapes and level floors of a CSR graph, chosen by timing BFS from
 // eight seeded roots of positive degree. Coordinate descent from the
 // defaults: each knob in turn tries its values with the others fixed, each
-// setting timed as the median of five passes over the roots, and a value
-// replaces the current one only when it is faster by more than kTuneMargin,
-// twice (the second time against a fresh timing of the current setting), so
-// settings within timing noise of each other keep the earlier one and
-// repeated tuning gives the same choice. Two sweeps over the knobs.
-constexpr double kTuneMargin = 0.05;
+// setting timed as the sum over the roots of each root's fastest of five
+// runs, and a value replaces the current one only when it is faster by more
+// than kTuneMargin, twice (the second time against a fresh timing of the
+// current setting), so settings within timing noise of each other keep the
+// earlier one and repeated tuning gives the same choice. Two sweeps over the
+// knobs.
+constexpr double kTuneMargin = 0.08;
 constexpr int kTunePasses = 5;
 
 int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
@@ -141,46 +143,67 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   // or n / 512: a frontier of a few hubs (R-MAT's second level) pushed
   // without a claim per edge
   const int ct_low = (int)std::max<int64_t>(g->csr.n / 512, 4096);
+  // a knob is a list of settings (values[0] the default); a setting gives
+  // one or more options their values together
+  using Field = int32_t bfs_options_t::*;
+  using Setting = std::vector<std::pair<Field, int32_t>>;
   struct Knob {
-    int32_t bfs_options_t::*field;
-    std::vector<int32_t> values;   // values[0] is the default
+    std::vector<Setting> values;
   };
+  auto one = [](Field f, std::initializer_list<int32_t> vs) {
+    Knob kb;
+    for (int32_t v : vs) kb.values.push_back(Setting{{f, v}});
+    return kb;
+  };
+  const Field cmf = &bfs_options_t::claim_min_frontier, cth = &bfs_options_t::claim_threshold;
   const std::vector<Knob> knobs = {
-      {&bfs_options_t::grid_blocks, {cus * 2, cus * 4}},
-      {&bfs_options_t::batch_levels, {4, 8}},
-      {&bfs_options_t::claim_min_frontier, {4096, 1024, 16384, 32}},
-      {&bfs_options_t::pull_alpha, {14, 4, 40}},
-      {&bfs_options_t::claim_threshold, {0, ct16, ct_low}},
-      {&bfs_options_t::small_frontier, {8192, 1024, -1}},
+      one(&bfs_options_t::grid_blocks, {cus * 2, cus * 4}),
+      one(&bfs_options_t::batch_levels, {4, 8}),
+      // the two floors of mark-and-resolve act together (a frontier must
+      // pass both), so they are tried in pairs
+      Knob{{Setting{{cmf, 4096}, {cth, 0}}, Setting{{cmf, 1024}, {cth, 0}},
+            Setting{{cmf, 16384}, {cth, 0}}, Setting{{cmf, 32}, {cth, ct_low}},
+            Setting{{cmf, 1024}, {cth, ct_low}}, Setting{{cmf, 4096}, {cth, ct16}}}},
+      one(&bfs_options_t::pull_alpha, {14, 4, 40}),
+      one(&bfs_options_t::small_frontier, {8192, 1024, -1}),
+  };
+  auto apply = [](bfs_options_t& o, const Setting& st) {
+    for (const auto& fv : st) o.*(fv.first) = fv.second;
+  };
+  auto holds = [](const bfs_options_t& o, const Setting& st) {
+    for (const auto& fv : st)
+      if (o.*(fv.first) != fv.second) return false;
+    return true;
   };
   bfs_options_t cur = saved;
-  for (const Knob& kb : knobs) cur.*(kb.field) = kb.values[0];
+  for (const Knob& kb : knobs) apply(cur, kb.values[0]);
   int rc = BFS_OK;
   auto measure = [&](const bfs_options_t& o, double* out) -> int {
     g->opt = o;
     int r = csr_run(g, cand[0], parent, level, nullptr, true);   // warm
     if (r != BFS_OK) return r;
-    double t[kTunePasses];
+    // per root the fastest of the passes (timing noise only adds), summed
+    std::vector<double> best_root(cand.size(), 1e30);
     for (int pass = 0; pass < kTunePasses; ++pass) {
-      const auto t0 = std::chrono::steady_clock::now();
-      for (int32_t root : cand) {
-        r = csr_run(g, root, parent, level, nullptr, true);
+      for (size_t i = 0; i < cand.size(); ++i) {
+        const auto t0 = std::chrono::steady_clock::now();
+        r = csr_run(g, cand[i], parent, level, nullptr, true);
         if (r != BFS_OK) return r;
+        const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        best_root[i] = std::min(best_root[i], dt);
       }
-      t[pass] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
-    std::sort(t, t + kTunePasses);
-    *out = t[kTunePasses / 2];
+    *out = std::accumulate(best_root.begin(), best_root.end(), 0.0);
     return BFS_OK;
   };
   double best = 0.0;
   rc = measure(cur, &best);
   for (int sweep = 0; sweep < 2 && rc == BFS_OK; ++sweep) {
     for (const Knob& kb : knobs) {
-      for (int32_t v : kb.values) {
-        if (cur.*(kb.field) == v) continue;
+      for (const Setting& v : kb.values) {
+        if (holds(cur, v)) continue;
         bfs_options_t o = cur;
-        o.*(kb.field) = v;
+        apply(o, v);
         double t = 0.0;
         rc = measure(o, &t);
         if (rc != BFS_OK) break;
@@ -206,7 +229,11 @@ int tune_csr(bfs_graph* g, const hipDeviceProp_t& prop, std::string* result) {
   (void)hipFree(level);
   g->opt = saved;
   if (rc != BFS_OK) return rc;
-  for (const Knob& kb : knobs) g->opt.*(kb.field) = cur.*(kb.field);
+  for (const Knob& kb : knobs) apply(g->opt, [&] {
+      Setting st = kb.values[0];
+      for (auto& fv : st) fv.second = cur.*(fv.first);
+      return st;
+    }());
   std::ostringstream o;
   o << "grid=" << cur.grid_blocks << " batch=" << cur.batch_levels
     << " min_frontier=" << cur.claim_min_frontier << " pull_alpha=" << cur.pull_alpha

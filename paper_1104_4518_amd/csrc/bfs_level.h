@@ -43,7 +43,11 @@ struct Queues {
 
 // Level selection: mark-and-resolve when the graph is symmetric and the
 // input frontier is large in both edges and vertices (a small frontier makes
-// every new vertex search far for one of its few frontier neighbours).
+// every new vertex search far for one of its few frontier neighbours), or
+// whatever its vertex count when pull_alpha times its adjacencies reach
+// all of the graph's: such a level always pulls (below), and a frontier of
+// a few hubs is where pulling pays most, since the unvisited vertices find
+// a hub among their first neighbours.
 struct MarkPolicy {
   int symmetric;
   long long min_edges;
@@ -58,8 +62,10 @@ struct MarkPolicy {
 __device__ __forceinline__ bool mark_level(unsigned long long cin, int cbits,
                                            const MarkPolicy& mp) {
   const unsigned long long cmask = (1ull << cbits) - 1;
-  return mp.symmetric && (long long)(cin >> cbits) >= mp.min_edges &&
-         (long long)(cin & cmask) >= mp.min_vertices;
+  const long long F = (long long)(cin & cmask), T = (long long)(cin >> cbits);
+  return mp.symmetric && F > 0 && T >= mp.min_edges &&
+         (F >= mp.min_vertices ||
+          (mp.pull_alpha > 0 && T >= (mp.nnz + mp.pull_alpha - 1) / mp.pull_alpha));
 }
 
 // A large claim level on a symmetric graph whose frontier holds at least
@@ -91,7 +97,8 @@ __device__ __forceinline__ bool pull_level(unsigned long long cin, int cbits,
   const unsigned long long T = cin >> cbits;
   const unsigned long long rest =
       (unsigned long long)mp.nnz > seen ? (unsigned long long)mp.nnz - seen : 0ull;
-  return T * (unsigned long long)mp.pull_alpha >= rest;
+  const unsigned long long a = (unsigned long long)mp.pull_alpha;
+  return T >= (rest + a - 1) / a;
 }
 
 

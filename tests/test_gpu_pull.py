@@ -177,3 +177,22 @@ def test_claim_level_with_many_new_vertices_from_few_edges():
         assert_bfs_equal(g, G, r)
     info = [L for L in G.level_info() if L["frontier"] > 0]
     assert all(L["mark"] in (0, 3, 4) for L in info)
+
+
+def test_pull_from_a_few_hubs_below_the_frontier_floor():
+    """A frontier of few vertices whose adjacencies times pull_alpha reach
+    nnz pulls although it holds fewer vertices than claim_min_frontier (the
+    second level of an R-MAT search from a vertex next to the hubs)."""
+    g = graphgen.rmat_csr(20, 16, 53)
+    G = graph_on_device(g)
+    G.set_options(profile=1, claim_min_frontier=16384, pull_alpha=1024)
+    seen_small_pull = False
+    for r in graphgen.roots(g, 4, 59):
+        say(f"rmat20 hub-frontier pull root {r}")
+        assert_bfs_equal(g, G, int(r))
+        for L in G.level_info():
+            if L["mark"] == 2 and 0 < L["frontier"] < 16384:
+                assert L["edges"] * 1024 >= g.nnz
+                seen_small_pull = True
+    assert seen_small_pull
+    G.set_options(profile=-1, claim_min_frontier=4096, pull_alpha=14)

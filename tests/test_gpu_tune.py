@@ -18,13 +18,14 @@ def test_tune_csr_choices_cache_and_results(tmp_path):
     G.tune(str(cache))
     o = G.get_options()
     assert o.batch_levels in (4, 8)
-    assert o.claim_min_frontier in (1024, 4096, 16384, 32)
+    ct_low = max(g.n // 512, 4096)
+    assert (o.claim_min_frontier, o.claim_threshold) in (
+        (4096, 0), (1024, 0), (16384, 0), (32, ct_low), (1024, ct_low), (4096, g.nnz // 16))
     assert o.pull_alpha in (4, 14, 40)
     assert o.grid_blocks > 0 and o.grid_blocks % 2 == 0
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and " csr n=16384 " in lines[0] and "min_frontier=" in lines[0]
     assert "pull_alpha=" in lines[0] and "claim_threshold=" in lines[0]
-    assert o.claim_threshold in (0, g.nnz // 16, max(g.n // 512, 4096))
     assert o.small_frontier in (8192, 1024, -1) and "small_frontier=" in lines[0]
     for r in graphgen.roots(g, 3, 5):
         say(f"tuned rmat14 root {r}")

@@ -135,9 +135,10 @@ def finish_bytes(levels, nwords: int) -> float:
     OR of its visited word (12 B); a large claim level (new frontier at
     least n/64) instead rebuilds the bitmap from the tags, 32 B read and 4 B
     written per word. Mark, pull and touch-mark claim levels: the tags of the
-    whole graph (32 B per word) read; per new vertex its two row offsets and
-    queue entry (36 B), its tag and visited bit rewritten with its word (1 B +
-    1/8 B)."""
+    whole graph (32 B per word) read; per new vertex its tag and visited bit
+    rewritten with its word (1 B + 1/8 B), and its two row offsets and queue
+    entry (36 B) unless the level pulls and so does the next one (no queue
+    is built then)."""
     total = 0.0
     n = nwords * 32
     for i, L in enumerate(levels):
@@ -147,7 +148,9 @@ def finish_bytes(levels, nwords: int) -> float:
         if L["mark"] == 0:
             total += 36.0 * nwords if new * 64 >= n else 12.0 * new
             continue
-        total += 32.0 * nwords + 37.125 * new
+        next_pulls = i + 1 < len(levels) and levels[i + 1]["mark"] == 2
+        queue = 0.0 if (L["mark"] == 2 and next_pulls) else 36.0
+        total += 32.0 * nwords + (1.125 + queue) * new
     return total
 
 
@@ -768,6 +771,8 @@ def main() -> int:
                          "(e.g. the tuned_options of an earlier line), for profiled runs")
     ap.add_argument("--spmspv-densities", default="0.0001,0.001,0.01,0.1",
                     help="frontier densities of the SpMSpV leg")
+    ap.add_argument("--no-floor", dest="floor", action="store_false",
+                    help="skip the one-edge search that measures a search's fixed cost")
     ap.add_argument("--no-upper-storage", dest="upper_storage", action="store_false",
                     help="skip the headline graph's run on symmetric (upper-triangle) storage")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -834,7 +839,8 @@ def main() -> int:
                            "roofline": r2["roofline"], "level_kernels": r2["level_kernels"],
                            "pass_gteps": r2["pass_gteps"], "config": cfg}
         out["workloads"] = extra
-        out["bfs_floor"] = bfs_floor(torch, graphgen, B, np)
+        if args.floor:
+            out["bfs_floor"] = bfs_floor(torch, graphgen, B, np)
     if "spmspv" in legs:
         out["spmspv"] = spmspv_leg(args, torch, graphgen, B, np)
     if "mix" in legs:

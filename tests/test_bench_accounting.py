@@ -67,6 +67,10 @@ def test_finish_bytes_by_level_kind():
     big = [lvl(0, 5, 50), lvl(0, nwords * 32 // 64, 10)]
     assert bench.finish_bytes(big, nwords) == pytest.approx(36 * nwords + 12 * 0 +
                                                             bench.finish_bytes(big[1:], nwords))
+    # a pull level followed by another pull level builds no queue
+    pp = [lvl(2, 100, 5000, pc=10, pe=10), lvl(2, 400, 9000, pc=5, pe=5), lvl(0, 3, 3)]
+    assert bench.finish_bytes(pp, nwords) == pytest.approx(
+        32 * nwords + 1.125 * 400 + 32 * nwords + 37.125 * 3)
 
 
 def test_examined_bytes_is_the_sum_of_the_kernels_plus_init_and_output():

@@ -151,6 +151,7 @@ constexpr int kPushLdsBytes = kHotWordsMax * 4 + (kMarkBlock / 64) * (kTileJ / 3
 constexpr int kResolveLdsBytes = kHotWordsMax * 4 + 2 * (kResolveBlock / 64) * 8;
 constexpr int kMarkLds1 = kPushLdsBytes > kPullLdsBytes ? kPushLdsBytes : kPullLdsBytes;
 constexpr int kMarkLdsBytes = kMarkLds1 > kResolveLdsBytes ? kMarkLds1 : kResolveLdsBytes;
+static_assert(kPullLdsBytes <= kPushLdsBytes, "the pull fits in the push level's LDS");
 static_assert(kResolveBlock == kMarkBlock, "the resolve runs in the mark expand's workgroups");
 static_assert(kPullBlock == kMarkBlock, "the pull runs in the mark expand's workgroups");
 

@@ -298,10 +298,13 @@ __device__ __forceinline__ void resolve_body(
 // It runs inside the mark expand's launch (bfs_mark.hip), one 1024-thread
 // workgroup per CU, on that kernel's LDS.
 constexpr int kPullBlock = 1024;
-// hot prefix staged by the pull: 144 KiB of bits plus 8 KiB of wave lists
-constexpr int kPullHotWords = 36864;
-constexpr int kPullLdsBytes =
-    kPullHotWords * 4 + 2 * (kPullBlock / 64) * 64 * 4 + 4 * (kPullBlock / 64) * 8;
+// hot prefix staged by the pull: 133.5 KiB of bits, 8 KiB of wave lists and
+// 16 KiB of deferred searches (kPullDefer per wave), within the mark
+// kernel's LDS (the push level's share, the largest)
+constexpr int kPullHotWords = 34176;
+constexpr int kPullDefer = 256;
+constexpr int kPullLdsBytes = kPullHotWords * 4 + 2 * (kPullBlock / 64) * 64 * 4 +
+                              4 * (kPullBlock / 64) * 8 + (kPullBlock / 64) * kPullDefer * 4;
 // searches per thread
 constexpr int kPullRV = 2;
 
@@ -318,6 +321,8 @@ __device__ __forceinline__ void pull_body(
   uint32_t (*s_m)[64] = reinterpret_cast<uint32_t (*)[64]>(lds + kPullHotWords * 4 + WAVES * 256);
   unsigned long long (*s_red)[WAVES] = reinterpret_cast<unsigned long long (*)[WAVES]>(
       lds + kPullHotWords * 4 + 2 * WAVES * 256);
+  int32_t (*s_def)[kPullDefer] = reinterpret_cast<int32_t (*)[kPullDefer]>(
+      lds + kPullHotWords * 4 + 2 * WAVES * 256 + 4 * WAVES * 8);
   const int k = st->k_fold;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -336,6 +341,42 @@ __device__ __forceinline__ void pull_body(
   const int64_t nchunks = (nw + 63) >> 6;
   const int64_t nwaves = (int64_t)gridDim.x * WAVES;
   unsigned long long my_cand = 0, my_edges = 0, my_found = 0, my_fdeg = 0;
+  auto found = [&](int32_t v, int32_t p, long long d) {
+    const int32_t pc = inv ? inv[p] : p;
+    rpl[v] = ((unsigned long long)k << 32) | (uint32_t)pc;
+    mark[v] = 1;
+    ++my_found;
+    my_fdeg += (unsigned long long)d;
+  };
+  // A search the head entry leaves open waits in the wave's LDS list; the
+  // row scans run kPullRV per lane once a full round has gathered, so one
+  // long scan does not hold up a round of searches the head copy decides.
+  int nd = 0;   // searches in the wave's list (the same in every lane)
+  auto scan_deferred = [&](int cnt) {
+    int32_t v[kPullRV], p[kPullRV];
+    int64_t o[kPullRV], end[kPullRV], at[kPullRV];
+#pragma unroll
+    for (int t = 0; t < kPullRV; ++t) {
+      const int i = t * 64 + lane;
+      v[t] = i < cnt ? s_def[wid][i] : -1;
+      p[t] = -1;
+      o[t] = 0;
+      end[t] = 0;
+      if (v[t] >= 0) {
+        o[t] = off[v[t]];
+        end[t] = off[v[t] + 1];
+      }
+    }
+    first_up_rest<kPullRV>(col, prev_bits, s_prev, hotv, lane, v, o, end, p, at);
+#pragma unroll
+    for (int t = 0; t < kPullRV; ++t) {
+      if (v[t] < 0) continue;
+      ++my_cand;   // an open search's row is longer than kHead
+      my_edges += p[t] >= 0 ? (unsigned long long)(at[t] - o[t] + 1)
+                            : (unsigned long long)(end[t] - o[t]);
+      if (p[t] >= 0) found(v[t], p[t], end[t] - o[t]);
+    }
+  };
   for (int64_t c = (int64_t)blockIdx.x * WAVES + wid; c < nchunks; c += nwaves) {
     const int64_t w = (c << 6) + lane;
     uint32_t m = 0u;
@@ -355,7 +396,6 @@ __device__ __forceinline__ void pull_body(
     for (int r = 0; r < total; r += 64 * kPullRV) {
       int32_t v[kPullRV], p[kPullRV], deg[kPullRV];
       int pos[kPullRV];
-      int64_t o[kPullRV], end[kPullRV], at[kPullRV];
 #pragma unroll
       for (int t = 0; t < kPullRV; ++t) {
         const int i = r + t * 64 + lane;
@@ -369,36 +409,51 @@ __device__ __forceinline__ void pull_body(
         }
       }
       head_step<kPullRV>(head, prev_bits, s_prev, hotv, v, p, pos, deg);
-      // rows are read only for the searches the head copy left open
-      bool in_head[kPullRV];
 #pragma unroll
       for (int t = 0; t < kPullRV; ++t) {
-        in_head[t] = p[t] >= 0;
-        o[t] = 0;
-        end[t] = 0;
-        if (v[t] >= 0 && p[t] < 0 && deg[t] > kHead) {
-          o[t] = off[v[t]];
-          end[t] = o[t] + deg[t];
-        }
-      }
-      first_up_rest<kPullRV>(col, prev_bits, s_prev, hotv, lane, v, o, end, p, at);
-#pragma unroll
-      for (int t = 0; t < kPullRV; ++t) {
-        if (v[t] < 0) continue;
+        // open: no frontier vertex among the first kHead adjacencies of a
+        // longer row (nd < 64 * kPullRV here, so the list has room)
+        const bool open = v[t] >= 0 && p[t] < 0 && deg[t] > kHead;
+        const unsigned long long mo = wave_ballot(open);
+        if (open) s_def[wid][nd + lanes_below(mo)] = v[t];
+        nd += __popcll(mo);
+        if (v[t] < 0 || open) continue;
         my_cand += deg[t] > 0;   // vertices of degree 0 have nothing to search
-        my_edges += in_head[t] ? (unsigned long long)(pos[t] + 1)
-                               : (p[t] >= 0 ? (unsigned long long)(at[t] - o[t] + 1)
-                                            : (unsigned long long)deg[t]);
-        if (p[t] < 0) continue;
-        const int32_t pc = inv ? inv[p[t]] : p[t];
-        rpl[v[t]] = ((unsigned long long)k << 32) | (uint32_t)pc;
-        mark[v[t]] = 1;
-        ++my_found;
-        my_fdeg += (unsigned long long)deg[t];
+        my_edges += p[t] >= 0 ? (unsigned long long)(pos[t] + 1) : (unsigned long long)deg[t];
+        if (p[t] >= 0) found(v[t], p[t], deg[t]);
+      }
+      if (nd >= 64 * kPullRV) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        scan_deferred(64 * kPullRV);
+        // the rest (fewer than a round) moves to the front of the list
+        const int left = nd - 64 * kPullRV;
+        int32_t keep[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const int i = x * 64 + lane;
+          keep[x] = i < left ? s_def[wid][64 * kPullRV + i] : 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const int i = x * 64 + lane;
+          if (i < left) s_def[wid][i] = keep[x];
+        }
+        nd = left;
       }
     }
     // the wave's lists are rewritten by its next chunk
     __builtin_amdgcn_wave_barrier();
+  }
+  if (nd > 0) {   // the searches left in the list (nd is uniform, so the whole wave scans)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    scan_deferred(nd);
   }
   // statistics: candidates and examined adjacencies of the level
 #pragma unroll

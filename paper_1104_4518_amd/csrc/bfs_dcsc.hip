@@ -575,7 +575,7 @@ __device__ __forceinline__ int sort_block_scan(int v, int* s_w, int& total) {
 }
 
 // counters[0] = output count, [1] = frontier error, [2] = product too large
-// for LDS (the caller then runs the SPA path).
+// for LDS (the caller then runs the binned path).
 __global__ __launch_bounds__(kSortBlock) void k_spmspv_sort(
     int64_t fnnz, const int32_t* __restrict__ fidx, const int32_t* __restrict__ fval,
     int32_t ncols, const int32_t* __restrict__ jc, const int32_t* __restrict__ cp,

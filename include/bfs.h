@@ -216,7 +216,10 @@ int bfs_graph_get_options(const bfs_graph_t* g, bfs_options_t* opt);
 /*
  * BFS from `root` on a CSR graph (Algorithms 1 and 3). parent is required,
  * level may be NULL; both hold n int32 and may be device or host memory.
- * Synchronous: returns when the outputs are complete.
+ * Synchronous: returns when the outputs are complete. The calling thread
+ * waits for the device by polling the stream (for the lowest latency), so
+ * it keeps one host core busy for the duration of the call; the same holds
+ * for the host reads of the frontier size between batches of levels.
  */
 int bfs_run(bfs_graph_t* g, int32_t root, int32_t* parent, int32_t* level);
 

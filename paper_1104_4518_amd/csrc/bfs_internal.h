@@ -84,6 +84,10 @@ struct LevelState {
   int32_t grp_level[4096];
   int32_t grp_first[4096];
   int32_t grp_last[4096];
+  // targets of the device level loop's atomics that must not change a word
+  // (one per thread of its workgroup), so that every claim of a round is
+  // issued unconditionally and the round waits once
+  unsigned long long sink[1024];
 };
 constexpr int kLevelHist = 4096;
 

@@ -88,6 +88,11 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_levels(SmallArgs a) {
   bool first = true;
   unsigned long long reached = 0;
   int depth = 0;
+  // the levels' edge, frontier and level counts, added to the state at the
+  // hand-off (no read of the state on a level's critical path)
+  unsigned long long acc_edges = 0, acc_front = 0;
+  int acc_levels = 0;
+  const int kind_entry = st->kind_cur;
   for (;;) {
     const int F = (int)(cin & cmask);
     const long long T = (long long)(cin >> a.cbits);
@@ -105,6 +110,16 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_levels(SmallArgs a) {
         s_u[j] = (uint32_t)(a.inv ? a.inv[v] : v);
       }
     } else {
+      // the thread's entries, all loads issued before any is used (indices
+      // past F read entry F - 1 and are dropped)
+      unsigned long long w[kSmallSPT];
+      long long o[kSmallSPT];
+#pragma unroll
+      for (int i = 0; i < kSmallSPT; ++i) {
+        const int j = min(tid * kSmallSPT + i, F - 1);
+        w[i] = (unsigned long long)qe_in[j];
+        o[i] = qo_in[j];
+      }
       long long d[kSmallSPT];
       long long mine = 0;
 #pragma unroll
@@ -112,10 +127,9 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_levels(SmallArgs a) {
         const int j = tid * kSmallSPT + i;
         d[i] = 0;
         if (j < F) {
-          const unsigned long long w = (unsigned long long)qe_in[j];
-          d[i] = (long long)(w >> 32);
-          s_u[j] = (uint32_t)w;
-          s_o[j] = qo_in[j];
+          d[i] = (long long)(w[i] >> 32);
+          s_u[j] = (uint32_t)w[i];
+          s_o[j] = o[i];
         }
         mine += d[i];
       }
@@ -135,12 +149,12 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_levels(SmallArgs a) {
       // the level's bookkeeping, as the expand kernel's
       st->k_fold = k;
       st->levels = k;
-      st->edges += (unsigned long long)T;
-      st->frontier_total += (unsigned long long)F;
+      acc_edges += (unsigned long long)T;
+      acc_front += (unsigned long long)F;
+      ++acc_levels;
       st->pull = 0;
-      st->kind_prev = st->kind_cur;
+      st->kind_prev = first ? kind_entry : 0;
       st->kind_cur = 0;
-      st->small_levels += 1;
       if (k < kLevelHist) {
         st->hist[k] = cin;
         st->hist_mark[k] = 4;
@@ -178,45 +192,72 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_levels(SmallArgs a) {
           vv[i] = a.col[s_o[lo] + (e - (long long)s_e[lo])];
         }
       }
-      unsigned long long cur[kSmallRound];
-#pragma unroll
-      for (int i = 0; i < kSmallRound; ++i) cur[i] = vv[i] >= 0 ? a.rpl[vv[i]] : 0ull;
+      // the claims: every item issues its atomic (an empty one on the
+      // thread's sink word), so the round waits for all of them at once;
+      // a target reached earlier keeps its smaller word
       bool own[kSmallRound];
+      {
+        unsigned long long old[kSmallRound];
 #pragma unroll
-      for (int i = 0; i < kSmallRound; ++i) {
-        const unsigned long long key = kk | s_u[row[i]];
-        own[i] = vv[i] >= 0 && cur[i] > key && atomicMin(a.rpl + vv[i], key) == ~0ull;
-      }
-#pragma unroll
-      for (int i = 0; i < kSmallRound; ++i) {
-        int64_t o0 = 0, d = 0;
-        uint32_t cid = 0;
-        const int32_t v = vv[i];
-        if (own[i]) {
-          o0 = a.off[v];
-          d = a.off[v + 1] - o0;
-          cid = (uint32_t)(a.inv ? a.inv[v] : v);
-          atomicOr(&a.vis[v >> 5], 1u << (v & 31));
-          if (a.mp.symmetric) a.mark[v] = level_tag(k);
-          ++my_own;
+        for (int i = 0; i < kSmallRound; ++i) {
+          const unsigned long long key = kk | s_u[row[i]];
+          old[i] = atomicMin(vv[i] >= 0 ? a.rpl + vv[i] : a.st->sink + tid, key);
         }
-        const bool enq = own[i] && d > 0;
-        const unsigned long long m = wave_ballot(enq);
-        if (m) {
-          const long long dincl = wave_incl_scan(enq ? d : 0);
-          const long long dsum = shfl_ll(dincl, 63);
-          int base = 0;
-          if (lane == 0) {
-            base = atomicAdd(&s_cnt, __popcll(m));
-            atomicAdd(&s_tsum, (unsigned long long)dsum);
-          }
-          base = __shfl(base, 0, 64);
-          if (enq) {
-            const int slot = base + lanes_below(m);
-            qv_out[slot] = v;
-            qo_out[slot] = o0;
-            qe_out[slot] = (int64_t)(((unsigned long long)d << 32) | cid);
-          }
+#pragma unroll
+        for (int i = 0; i < kSmallRound; ++i) own[i] = vv[i] >= 0 && old[i] == ~0ull;
+      }
+      // the owners' rows and caller ids, loaded together (others read
+      // vertex 0's and drop them)
+      int64_t ob[kSmallRound];
+      int32_t dg[kSmallRound];   // degree (< 2^31)
+      uint32_t cids[kSmallRound];
+      {
+        int64_t oe[kSmallRound];
+#pragma unroll
+        for (int i = 0; i < kSmallRound; ++i) {
+          const int32_t vs = own[i] ? vv[i] : 0;
+          ob[i] = a.off[vs];
+          oe[i] = a.off[vs + 1];
+          cids[i] = (uint32_t)(a.inv ? a.inv[vs] : vs);
+        }
+#pragma unroll
+        for (int i = 0; i < kSmallRound; ++i) dg[i] = own[i] ? (int32_t)(oe[i] - ob[i]) : 0;
+      }
+      // the owners: visited bit and tag; those with adjacencies join the
+      // next queue through one LDS reservation per wave and round
+      int my_cnt = 0;
+      long long my_d = 0;
+#pragma unroll
+      for (int i = 0; i < kSmallRound; ++i) {
+        if (!own[i]) continue;
+        const int32_t v = vv[i];
+        atomicOr(&a.vis[v >> 5], 1u << (v & 31));
+        if (a.mp.symmetric) a.mark[v] = level_tag(k);
+        ++my_own;
+        if (dg[i] > 0) {
+          ++my_cnt;
+          my_d += dg[i];
+        }
+      }
+      const long long cincl = wave_incl_scan((long long)my_cnt);
+      const long long dincl = wave_incl_scan(my_d);
+      int base = 0;
+      unsigned long long dbase = 0;
+      if (lane == 63 && cincl > 0) {
+        base = atomicAdd(&s_cnt, (int)cincl);
+        dbase = atomicAdd(&s_tsum, (unsigned long long)dincl);
+      }
+      (void)dbase;
+      base = __shfl(base, 63, 64);
+      if (my_cnt > 0) {
+        int slot = base + (int)(cincl - my_cnt);
+#pragma unroll
+        for (int i = 0; i < kSmallRound; ++i) {
+          if (dg[i] <= 0) continue;
+          qv_out[slot] = vv[i];
+          qo_out[slot] = ob[i];
+          qe_out[slot] = (int64_t)(((unsigned long long)(uint32_t)dg[i] << 32) | cids[i]);
+          ++slot;
         }
       }
     }
@@ -270,6 +311,9 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_levels(SmallArgs a) {
         st->zcnt[(k + 1) % 3] = 0u;
         st->reached += reached;
         if (depth > st->depth) st->depth = depth;
+        st->edges += acc_edges;
+        st->frontier_total += acc_front;
+        st->small_levels += acc_levels;
         st->k_expand = k + 1;
       }
       return;

@@ -12,16 +12,18 @@
 // or needs the mark-and-resolve / pull evaluation.
 //
 // One level k here: the frontier (level k-1) is staged in LDS (row start,
-// exclusive edge prefix, caller id); every thread takes up to kSmallEPT of
-// its adjacencies, all loads in flight together; an unvisited target takes
-// the (select, min) semiring's claim, a 64-bit atomicMin of
-// (k << 32 | caller id of u) on its word, filtered by a plain read of the
-// word (not of the visited bitmap, so the bitmap can take the new vertices'
-// bits at once); the claimer of a fresh word appends the vertex to the next
-// queue (an LDS counter) with its degree and caller id, sets its visited bit
-// and tag. The queue entries carry (degree << 32 | caller id) in the edge
-// prefix slot while the loop runs; the hand-off rewrites them as prefixes
-// and builds the tile map.
+// exclusive edge prefix, caller id); every thread takes up to kSmallRound of
+// the level's adjacencies per round; each phase of a round (adjacencies,
+// claims, the owners' rows) issues all of its memory operations before it
+// waits, since one workgroup is bound by the latency of their chain. Every
+// target takes the (select, min) semiring's claim, a 64-bit atomicMin of
+// (k << 32 | caller id of u) on its word, without a filtering read (a word
+// set at an earlier level is smaller and stays); the claimer of a fresh word
+// appends the vertex to the next queue (one LDS reservation per wave and
+// round) with its degree and caller id, sets its visited bit and tag. The
+// queue entries carry (degree << 32 | caller id) in the edge prefix slot
+// while the loop runs; the hand-off rewrites them as prefixes and builds the
+// tile map.
 #include "bfs_level.h"
 
 #include <algorithm>

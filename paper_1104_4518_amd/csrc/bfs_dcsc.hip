@@ -105,6 +105,17 @@ constexpr int kStagePer = kStage / kBinBlock;
 constexpr int kNarrowEntries = 2, kSingleEntries = 1;
 constexpr int kProbe = 4;               // stored columns of a bucket read at once
 constexpr int kReduceBlock = 1024;
+constexpr int kHeld = 8;                // pairs per thread the reduction keeps in registers
+
+// Workgroup barrier that orders LDS only: global loads and stores still in
+// flight (prefetched frontier entries, pair stores) are not waited for. The
+// kernels below use it wherever the threads of a workgroup exchange data
+// through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 constexpr int kValCap = 16384;          // rows of one bin reduced in LDS; more use the SPA
 // chained-scan flag word: epoch (30 bits) | status (2 bits) | count (32 bits)
 constexpr uint64_t kFlagAgg = 1, kFlagIncl = 2;
@@ -134,6 +145,9 @@ struct BinArgs {
 // LDS stage, which is binned whenever it fills.
 template <int EPT>
 __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmspv_bin(BinArgs a) {
+  // the bucket probe pays for scattered lookups only (with two entries per
+  // thread, i.e. dense frontiers, the binary search measured faster)
+  constexpr bool PROBE = EPT == 1;
   constexpr int WAVES = kBinBlock / 64;
   constexpr int SUB = kBinBlock * EPT;
   __shared__ int32_t s_pre[SUB];            // product prefix of the sub-chunk's entries
@@ -155,14 +169,14 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
   // bins the staged products: per-bin ranks in LDS, one global reservation
   // per non-empty bin, then the pairs written to their bins' slices
   auto flush = [&](int S) {
-    __syncthreads();
+    lds_barrier();
     int rk[kStagePer];
 #pragma unroll
     for (int i = 0; i < kStagePer; ++i) {
       const int j = tid + i * kBinBlock;
       rk[i] = j < S ? atomicAdd(&s_hist[s_row[j] >> kBinShift], 1) : 0;
     }
-    __syncthreads();
+    lds_barrier();
     for (int b = tid; b < a.nbins; b += kBinBlock) {
       const int h = s_hist[b];
       if (h) {
@@ -173,7 +187,7 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
         s_hist[b] = 0;
       }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < kStagePer; ++i) {
       const int j = tid + i * kBinBlock;
@@ -186,52 +200,61 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
           bad = true;
       }
     }
-    __syncthreads();
+    lds_barrier();
   };
 
   const int64_t nsub = (a.fnnz + SUB - 1) / SUB;
   // the frontier entries of a sub-chunk (thread t owns entries t*EPT ..
   // t*EPT + EPT - 1) and the entry before them; the next sub-chunk's are
   // loaded while the current one is expanded
+  // (loaded unconditionally at clamped indices, so that no load waits
+  // before the entries are used; the entries past the frontier are dropped
+  // there)
   int32_t nk[EPT], nv[EPT], nprev = -1;
   auto load_entries = [&](int64_t c) {
-    const int64_t c0 = c * SUB;
-    const int nE = c < nsub ? (int)min((int64_t)SUB, a.fnnz - c0) : 0;
-    const int64_t i0 = c0 + (int64_t)tid * EPT;
+    const int64_t i0 = c * SUB + (int64_t)tid * EPT;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-      const bool in = tid * EPT + j < nE;
-      nk[j] = in ? a.fidx[i0 + j] : -1;
-      nv[j] = in && a.fval ? a.fval[i0 + j] : nk[j];
+      const int64_t i = min(i0 + j, a.fnnz - 1);
+      nk[j] = a.fidx[i];
+      nv[j] = a.fval ? a.fval[i] : 0;
     }
-    nprev = (tid * EPT < nE && i0 > 0) ? a.fidx[i0 - 1] : -1;
+    nprev = a.fidx[max(min(i0, a.fnnz) - 1, (int64_t)0)];
   };
   load_entries(blockIdx.x);
   for (int64_t c = blockIdx.x; c < nsub; c += gridDim.x) {
     const int64_t c0 = c * SUB;
     const int nE = (int)min((int64_t)SUB, a.fnnz - c0);
-    // lookup
+    // lookup; every step issues the loads of all the thread's entries before
+    // it uses any of them (entries without a column read index 0 and drop it)
     int32_t kk[EPT], kv[EPT], lo[EPT], hi[EPT], bend[EPT];
     {
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
-        kk[j] = nk[j];
-        kv[j] = nv[j];
+        kk[j] = tid * EPT + j < nE ? nk[j] : -1;
+        kv[j] = a.fval ? nv[j] : nk[j];
       }
-      const int32_t prev = nprev;
+      const int32_t prev = c0 + (int64_t)tid * EPT > 0 ? nprev : -1;
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
-        lo[j] = hi[j] = bend[j] = 0;
         if (tid * EPT + j >= nE) continue;
         const int32_t before = j ? kk[j - 1] : prev;
         if (kk[j] < 0 || kk[j] >= a.ncols || before >= kk[j]) {
           bad = true;
           kk[j] = -1;
-          continue;
         }
-        const int64_t bk = (int64_t)kk[j] >> a.shift;
-        lo[j] = a.aux[bk];
-        hi[j] = bend[j] = a.aux[bk + 1];
+      }
+      int32_t a0[EPT], a1[EPT];
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int64_t bk = kk[j] >= 0 ? ((int64_t)kk[j] >> a.shift) : 0;
+        a0[j] = a.aux[bk];
+        a1[j] = a.aux[bk + 1];
+      }
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        lo[j] = kk[j] >= 0 ? a0[j] : 0;
+        hi[j] = bend[j] = kk[j] >= 0 ? a1[j] : 0;
       }
     }
     // column positions: with one entry per thread (small frontiers, whose
@@ -241,40 +264,66 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
     int32_t q0[EPT], len[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) q0[j] = -1;
-    if constexpr (EPT == 1) {
-      int32_t w[kProbe];
+    if constexpr (PROBE) {
+      int32_t w[EPT][kProbe];
 #pragma unroll
-      for (int i = 0; i < kProbe; ++i) w[i] = lo[0] + i < hi[0] ? a.jc[lo[0] + i] : INT32_MAX;
-      int c = 0;
+      for (int j = 0; j < EPT; ++j)
 #pragma unroll
-      for (int i = 0; i < kProbe; ++i) c += w[i] < kk[0];
-      int32_t at = INT32_MAX;
+        for (int i = 0; i < kProbe; ++i) w[j][i] = a.jc[lo[j] + i < hi[j] ? lo[j] + i : 0];
 #pragma unroll
-      for (int i = kProbe - 1; i >= 0; --i)
-        if (i == c) at = w[i];
-      if (kk[0] >= 0 && c < kProbe && at == kk[0]) q0[0] = lo[0] + c;
-      if (kk[0] >= 0 && c == kProbe && lo[0] + kProbe < hi[0]) lo[0] += kProbe;
-      else lo[0] = hi[0];
+      for (int j = 0; j < EPT; ++j) {
+        int c = 0;
+#pragma unroll
+        for (int i = 0; i < kProbe; ++i) c += lo[j] + i < hi[j] && w[j][i] < kk[j];
+        int32_t at = INT32_MAX;
+#pragma unroll
+        for (int i = kProbe - 1; i >= 0; --i)
+          if (i == c && lo[j] + i < hi[j]) at = w[j][i];
+        if (kk[j] >= 0 && c < kProbe && at == kk[j]) q0[j] = lo[j] + c;
+        if (kk[j] >= 0 && c == kProbe && lo[j] + kProbe < hi[j]) lo[j] += kProbe;
+        else lo[j] = hi[j];
+      }
     }
     for (;;) {
       bool any = false;
+      int32_t mid[EPT], vm[EPT];
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        mid[j] = (lo[j] + hi[j]) >> 1;
+        vm[j] = a.jc[lo[j] < hi[j] ? mid[j] : 0];
+      }
 #pragma unroll
       for (int j = 0; j < EPT; ++j)
         if (lo[j] < hi[j]) {
-          const int32_t mid = (lo[j] + hi[j]) >> 1;
-          if (a.jc[mid] < kk[j]) lo[j] = mid + 1; else hi[j] = mid;
+          if (vm[j] < kk[j]) lo[j] = mid[j] + 1; else hi[j] = mid[j];
           any = true;
         }
       if (!any) break;
     }
+    {
+      int32_t vl[EPT];
 #pragma unroll
-    for (int j = 0; j < EPT; ++j)
-      if (q0[j] < 0 && kk[j] >= 0 && lo[j] < bend[j] && a.jc[lo[j]] == kk[j]) q0[j] = lo[j];
+      for (int j = 0; j < EPT; ++j) {
+        const bool open = q0[j] < 0 && kk[j] >= 0 && lo[j] < bend[j];
+        vl[j] = a.jc[open ? lo[j] : 0];
+      }
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int32_t p = q0[j];
-      q0[j] = p >= 0 ? a.cp[p] : 0;
-      len[j] = p >= 0 ? a.cp[p + 1] - q0[j] : 0;
+      for (int j = 0; j < EPT; ++j)
+        if (q0[j] < 0 && kk[j] >= 0 && lo[j] < bend[j] && vl[j] == kk[j]) q0[j] = lo[j];
+    }
+    {
+      int32_t c0[EPT], c1[EPT];
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int32_t p = q0[j] >= 0 ? q0[j] : 0;
+        c0[j] = a.cp[p];
+        c1[j] = a.cp[p + 1];
+      }
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        len[j] = q0[j] >= 0 ? c1[j] - c0[j] : 0;
+        q0[j] = q0[j] >= 0 ? c0[j] : 0;
+      }
     }
     int mine = 0;
 #pragma unroll
@@ -283,7 +332,7 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
     // exclusive product prefix over the sub-chunk's entries (entry order)
     const int incl = (int)wave_incl_scan((long long)mine);
     if (lane == 63) s_w[wid] = incl;
-    __syncthreads();
+    lds_barrier();
     int wb = 0, P = 0;
 #pragma unroll
     for (int x = 0; x < WAVES; ++x) {
@@ -303,7 +352,7 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
         ex += len[j];
       }
     }
-    __syncthreads();
+    lds_barrier();
     // expand: product jj belongs to the last entry whose prefix is <= jj
     // (entries without products share their successor's prefix)
     for (int done = 0; done < P;) {
@@ -325,7 +374,7 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
         staged = 0;
       }
     }
-    __syncthreads();   // s_pre / s_q0 are rewritten by the next sub-chunk
+    lds_barrier();   // s_pre / s_q0 are rewritten by the next sub-chunk
   }
   if (staged > 0) flush(staged);
   if (__any(bad) && lane == 0) a.counters[1] = a.epoch;
@@ -370,7 +419,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
     s_cnt = __hip_atomic_load(&a.cursor[s_b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   for (int w = tid; w < kBinWords; w += kReduceBlock) s_bits[w] = 0u;
-  __syncthreads();
+  lds_barrier();
   const int b = s_b;
   if (b >= a.nbins) {   // tickets out of step with the grid: report, touch nothing
     if (tid == 0) a.counters[3] = a.epoch;
@@ -379,20 +428,33 @@ __global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
   const int64_t st = a.bin_start[b];
   const int cnt = (int)min((int64_t)s_cnt, a.bin_start[b + 1] - st);
   const bool err = s_err;
+  // the thread's first kHeld pairs, all loaded before any is used and kept
+  // for the second pass; a bin with more pairs reads the rest in place
+  unsigned long long pr[kHeld];
+#pragma unroll
+  for (int i = 0; i < kHeld; ++i) {
+    const int j = tid + i * kReduceBlock;
+    pr[i] = (!err && j < cnt) ? a.pairs[st + j] : 0ull;
+  }
   if (!err) {
-    for (int j = tid; j < cnt; j += kReduceBlock) {
+#pragma unroll
+    for (int i = 0; i < kHeld; ++i) {
+      const uint32_t r = (uint32_t)(pr[i] >> 32);
+      if (tid + i * kReduceBlock < cnt) atomicOr(&s_bits[r >> 5], 1u << (r & 31));
+    }
+    for (int j = tid + kHeld * kReduceBlock; j < cnt; j += kReduceBlock) {
       const uint32_t r = (uint32_t)(a.pairs[st + j] >> 32);
       atomicOr(&s_bits[r >> 5], 1u << (r & 31));
     }
   }
-  __syncthreads();
+  lds_barrier();
   // rank of the first hit row of every word (block prefix over popcounts)
   int c = 0;
 #pragma unroll
   for (int i = 0; i < WPT; ++i) c += __popc(s_bits[tid * WPT + i]);
   const int incl = (int)wave_incl_scan((long long)c);
   if (lane == 63) s_w[wid] = incl;
-  __syncthreads();
+  lds_barrier();
   int wb = 0, U = 0;
 #pragma unroll
   for (int x = 0; x < WAVES; ++x) {
@@ -453,21 +515,24 @@ __global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
       s_excl = excl;
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (!err) {
     const long long excl = s_excl;
     const int64_t row0 = (int64_t)b << kBinShift;
     if (U <= kValCap) {
       for (int i = tid; i < U; i += kReduceBlock) s_val[i] = 0xFFFFFFFFu;
-      __syncthreads();
-      for (int j = tid; j < cnt; j += kReduceBlock) {
-        const unsigned long long p = a.pairs[st + j];
+      lds_barrier();
+      auto take = [&](unsigned long long p) {
         const uint32_t r = (uint32_t)(p >> 32);
         const int w = (int)(r >> 5);
         const int rank = s_wpre[w] + __popc(s_bits[w] & ((1u << (r & 31)) - 1u));
         atomicMin(&s_val[rank], (uint32_t)p);
-      }
-      __syncthreads();
+      };
+#pragma unroll
+      for (int i = 0; i < kHeld; ++i)
+        if (tid + i * kReduceBlock < cnt) take(pr[i]);
+      for (int j = tid + kHeld * kReduceBlock; j < cnt; j += kReduceBlock) take(a.pairs[st + j]);
+      lds_barrier();
       for (int i = 0; i < WPT; ++i) {
         const int w = i * kReduceBlock + tid;
         uint32_t bits = s_bits[w];

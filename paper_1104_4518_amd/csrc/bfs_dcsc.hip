@@ -386,7 +386,8 @@ struct ReduceArgs {
   int32_t* cursor;
   const unsigned long long* pairs;
   unsigned long long* chain;
-  int32_t* ticket;          // [0] bin ticket, [1] finished workgroups
+  uint32_t* ticket;         // bin tickets taken by all calls so far (wraps)
+  uint32_t ticket_base;     // the counter's value when this call's reduction starts
   uint32_t* spa_val;        // nrows, all ones between calls (bins over kValCap rows)
   unsigned long long* counters;
   unsigned long long* host;  // pinned host words the results are written to
@@ -408,34 +409,45 @@ __global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
   __shared__ int32_t s_wpre[kBinWords];
   __shared__ uint32_t s_val[kValCap];
   __shared__ int s_w[WAVES];
-  __shared__ int s_b, s_cnt, s_err;
+  __shared__ uint32_t s_b;
   __shared__ long long s_excl;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wid = tid >> 6;
-  if (tid == 0) {
-    s_b = atomicAdd(&a.ticket[0], 1);
-    s_err = a.counters[1] == a.epoch;
-    s_cnt = __hip_atomic_load(&a.cursor[s_b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  for (int w = tid; w < kBinWords; w += kReduceBlock) s_bits[w] = 0u;
-  lds_barrier();
-  const int b = s_b;
-  if (b >= a.nbins) {   // tickets out of step with the grid: report, touch nothing
-    if (tid == 0) a.counters[3] = a.epoch;
-    return;
-  }
-  const int64_t st = a.bin_start[b];
-  const int cnt = (int)min((int64_t)s_cnt, a.bin_start[b + 1] - st);
-  const bool err = s_err;
+  // The bin comes from the ticket counter (bins are taken in the order
+  // workgroups start, which the chained scan's waits rely on). Workgroups
+  // almost always start in index order, so the bin of this workgroup's
+  // index is read while the ticket is fetched, and read again only if the
+  // ticket names another bin.
+  if (tid == 0) s_b = atomicAdd(a.ticket, 1u) - a.ticket_base;
   // the thread's first kHeld pairs, all loaded before any is used and kept
   // for the second pass; a bin with more pairs reads the rest in place
   unsigned long long pr[kHeld];
+  int64_t st;
+  int cnt;
+  bool err;
+  auto read_bin = [&](int bin) {
+    st = a.bin_start[bin];
+    cnt = (int)min((int64_t)__hip_atomic_load(&a.cursor[bin], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT),
+                   a.bin_start[bin + 1] - st);
+    err = a.counters[1] == a.epoch;
 #pragma unroll
-  for (int i = 0; i < kHeld; ++i) {
-    const int j = tid + i * kReduceBlock;
-    pr[i] = (!err && j < cnt) ? a.pairs[st + j] : 0ull;
+    for (int i = 0; i < kHeld; ++i) {
+      const int j = tid + i * kReduceBlock;
+      pr[i] = (!err && j < cnt) ? a.pairs[st + j] : 0ull;
+    }
+  };
+  read_bin(blockIdx.x);
+  for (int w = tid; w < kBinWords; w += kReduceBlock) s_bits[w] = 0u;
+  lds_barrier();
+  const uint32_t ub = s_b;
+  if (ub >= (uint32_t)a.nbins) {   // tickets out of step with the grid: report, touch nothing
+    if (tid == 0) a.host[3] = a.epoch;
+    return;
   }
+  const int b = (int)ub;
+  if (b != (int)blockIdx.x) read_bin(b);
   if (!err) {
 #pragma unroll
     for (int i = 0; i < kHeld; ++i) {
@@ -470,44 +482,61 @@ __global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
     }
   }
   // chained scan: publish this bin's count, then find the rows of all bins
-  // before it (wave 0 looks back 64 bins at a time)
+  // before it (wave 0 reads back 256 bins at a time, four words per lane,
+  // all issued before any is examined)
   if (!err && wid == 0) {
     if (lane == 0)
       __hip_atomic_store(&a.chain[b], chain_word(a.epoch, kFlagAgg, (uint32_t)U),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    constexpr int R = 4;
     long long excl = 0;
     int j = b - 1;
     long long spins = 0;
     while (j >= 0) {
-      const int idx = j - lane;
-      unsigned long long f = chain_word(a.epoch, kFlagIncl, 0u);   // before bin 0: nothing
-      if (idx >= 0) f = __hip_atomic_load(&a.chain[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t fe = (uint32_t)(f >> 34);
-      const int status = fe == a.epoch ? (int)((f >> 32) & 3u) : 0;
-      const unsigned long long nr = wave_ballot(status == 0);
-      const unsigned long long inc = wave_ballot(status == 2);
-      const int first_nr = nr ? __ffsll((long long)nr) - 1 : 64;
-      const int first_inc = inc ? __ffsll((long long)inc) - 1 : 64;
-      if (first_nr < first_inc) {
-        // a bin not published yet: take the counts before it and wait
-        long long v = lane < first_nr ? (long long)(uint32_t)f : 0;
+      unsigned long long f[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int idx = j - lane - 64 * k;
+        f[k] = idx >= 0 ? __hip_atomic_load(&a.chain[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : chain_word(a.epoch, kFlagIncl, 0u);   // before bin 0: nothing
+      }
+      bool done = false, wait = false;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const uint32_t fe = (uint32_t)(f[k] >> 34);
+        const int status = fe == a.epoch ? (int)((f[k] >> 32) & 3u) : 0;
+        const unsigned long long nr = wave_ballot(status == 0);
+        const unsigned long long inc = wave_ballot(status == 2);
+        const int first_nr = nr ? __ffsll((long long)nr) - 1 : 64;
+        const int first_inc = inc ? __ffsll((long long)inc) - 1 : 64;
+        if (first_nr < first_inc) {
+          // a bin not published yet: take the counts before it and wait
+          long long v = lane < first_nr ? (long long)(uint32_t)f[k] : 0;
+#pragma unroll
+          for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+          excl += v;
+          j -= first_nr;
+          wait = true;
+          break;
+        }
+        long long v = lane <= first_inc ? (long long)(uint32_t)f[k] : 0;
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
         excl += v;
-        j -= first_nr;
+        if (first_inc < 64) {
+          done = true;
+          break;
+        }
+        j -= 64;
+      }
+      if (done) break;
+      if (wait) {
         if (++spins > kLookbackSpins) {
-          if (lane == 0) a.counters[3] = a.epoch;
+          if (lane == 0) a.host[3] = a.epoch;
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        continue;
       }
-      long long v = lane <= first_inc ? (long long)(uint32_t)f : 0;
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-      excl += v;
-      if (first_inc < 64) break;
-      j -= 64;
     }
     if (lane == 0) {
       __hip_atomic_store(&a.chain[b], chain_word(a.epoch, kFlagIncl, (uint32_t)(excl + U)),
@@ -578,21 +607,14 @@ __global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
       }
     }
   }
-  __syncthreads();
   if (tid == 0) {
     a.cursor[b] = 0;   // the bin's slice is empty for the next call
-    if (b == a.nbins - 1) a.counters[0] = err ? 0ull : (unsigned long long)(s_excl + U);
-    __threadfence();
-    // the last workgroup to finish rewinds the tickets and hands the call's
-    // results to the host: output count, error epochs, and the epoch itself
-    // as the mark that the call completed
-    if (atomicAdd(&a.ticket[1], 1) == a.nbins - 1) {
-      __threadfence();
-      a.ticket[0] = 0;
-      a.ticket[1] = 0;
-      a.host[0] = __hip_atomic_load(&a.counters[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      a.host[1] = __hip_atomic_load(&a.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      a.host[3] = __hip_atomic_load(&a.counters[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the last bin's workgroup hands the call's results to the host (read
+    // once the stream has drained): output count, frontier error, and the
+    // epoch as the mark that the call completed
+    if (b == a.nbins - 1) {
+      a.host[0] = err ? 0ull : (unsigned long long)(s_excl + U);
+      a.host[1] = err ? a.epoch : 0ull;
       a.host[2] = a.epoch;
     }
   }
@@ -829,15 +851,16 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   BFS_HIP(hipMemsetAsync(d.cursor, 0, (size_t)d.nbins * 4, s));
   BFS_HIP(hipMalloc(&d.chain, (size_t)d.nbins * 8));
   BFS_HIP(hipMemsetAsync(d.chain, 0, (size_t)d.nbins * 8, s));
-  BFS_HIP(hipMalloc(&d.ticket, 2 * 4));
-  BFS_HIP(hipMemsetAsync(d.ticket, 0, 2 * 4, s));
+  BFS_HIP(hipMalloc(&d.ticket, 4));
+  BFS_HIP(hipMemsetAsync(d.ticket, 0, 4, s));
+  d.ticket_base = 0;
   BFS_HIP(hipMalloc(&d.pairs, (size_t)std::max<int64_t>(d.nnz, 1) * 8));
   BFS_HIP(hipMalloc(&d.spa_val, (size_t)std::max(d.nrows, 1) * 4));
   k_fill_u32<<<1024, 256, 0, s>>>(d.spa_val, d.nrows, 0xFFFFFFFFu);
   BFS_HIP(hipMalloc(&d.counters, 4 * sizeof(unsigned long long)));
   BFS_HIP(hipMemsetAsync(d.counters, 0, 4 * sizeof(unsigned long long), s));
   BFS_HIP(hipHostMalloc(&d.h_counters, 4 * sizeof(unsigned long long), hipHostMallocDefault));
-  d.h_counters[2] = 0ull;
+  for (int i = 0; i < 4; ++i) d.h_counters[i] = 0ull;   // no epoch matches before a call
   BFS_HIP(hipHostGetDevicePointer((void**)&d.h_counters_dev, d.h_counters, 0));
   BFS_HIP(hipStreamSynchronize(s));
   // the binning kernel's per-bin counters live in dynamic LDS (12 B per bin)
@@ -859,7 +882,7 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   d.grid_bin = cus * occ;   // co-resident workgroups of the binning kernel
   d.epoch = 1;
   g->device_bytes += d.naux * 4 + (int64_t)std::max(d.nrows, 1) * 4 +
-                     (int64_t)(d.nbins + 1) * 8 + (int64_t)d.nbins * 12 + 8 +
+                     (int64_t)(d.nbins + 1) * 8 + (int64_t)d.nbins * 12 + 4 +
                      std::max<int64_t>(d.nnz, 1) * 8 + 32;
   return BFS_OK;
 }
@@ -919,6 +942,8 @@ int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t 
   if (++d.epoch >= (1u << 30)) {
     BFS_HIP(hipMemsetAsync(d.chain, 0, (size_t)d.nbins * 8, s));
     BFS_HIP(hipMemsetAsync(d.counters, 0, 4 * sizeof(unsigned long long), s));
+    BFS_HIP(hipMemsetAsync(d.ticket, 0, 4, s));
+    d.ticket_base = 0;
     d.epoch = 2;
   }
   BinArgs ba;
@@ -952,6 +977,7 @@ int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t 
   ra.pairs = d.pairs;
   ra.chain = d.chain;
   ra.ticket = d.ticket;
+  ra.ticket_base = d.ticket_base;
   ra.spa_val = d.spa_val;
   ra.counters = d.counters;
   ra.host = d.h_counters_dev;
@@ -961,16 +987,22 @@ int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t 
   ra.out_val = out->val;
   k_spmspv_reduce<<<d.nbins, kReduceBlock, 0, s>>>(ra);
   BFS_HIP(hipGetLastError());
+  d.ticket_base += (uint32_t)d.nbins;   // one ticket per workgroup
   BFS_HIP(wait_stream(s));
   const volatile unsigned long long* h = d.h_counters;
-  if (h[2] != d.epoch)
-    return fail(BFS_ERR_DEVICE, "spmspv: the reduction over the row bins did not complete");
+  if (h[2] != d.epoch || h[3] == d.epoch) {
+    // the tickets may be out of step with the calls: start them again
+    BFS_HIP(hipMemsetAsync(d.ticket, 0, 4, s));
+    d.ticket_base = 0;
+    BFS_HIP(wait_stream(s));
+    return fail(BFS_ERR_DEVICE, h[2] != d.epoch
+                                    ? "spmspv: the reduction over the row bins did not complete"
+                                    : "spmspv: chained scan over the row bins did not complete");
+  }
   if (h[1] == d.epoch) {
     out->nnz = 0;
     return fail(BFS_ERR_ARG, "frontier indices must be strictly ascending and in [0, ncols)");
   }
-  if (h[3] == d.epoch)
-    return fail(BFS_ERR_DEVICE, "spmspv: chained scan over the row bins did not complete");
   const int64_t cnt = (int64_t)h[0];
   out->nnz = cnt;
   if (cnt > out->capacity) return fail(BFS_ERR_CAPACITY, "output capacity too small");

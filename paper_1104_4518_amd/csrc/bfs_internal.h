@@ -165,12 +165,13 @@ struct DcscDev {
   int32_t* cursor = nullptr;     // products appended to each bin (zero between calls)
   unsigned long long* pairs = nullptr;   // nnz
   unsigned long long* chain = nullptr;   // chained-scan flag word per bin
-  int32_t* ticket = nullptr;     // [0] next bin, [1] finished workgroups (zero between calls)
+  uint32_t* ticket = nullptr;    // bin tickets taken by all reductions so far (wraps)
+  uint32_t ticket_base = 0;      // its value before the next reduction
   uint32_t* spa_val = nullptr;   // nrows, all 0xFFFFFFFF between calls (bins too large for LDS)
   uint32_t epoch = 0;            // calls of the binned path (flags carry it)
   int grid_bin = 0;              // workgroups of the binning kernel
-  // [0] out count, [1] frontier error (epoch), [2] sort path: product too
-  // large, [3] chained-scan failure (epoch)
+  // [0] sort path's out count, [1] frontier error (the binned path writes
+  // its epoch there), [2] sort path: product too large
   unsigned long long* counters = nullptr;
   // pinned host words: the sort path copies counters [0..2] there; the
   // binned path's reduction writes [0] count, [1] and [3] the error epochs,

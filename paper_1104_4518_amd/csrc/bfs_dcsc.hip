@@ -414,11 +414,9 @@ __global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wid = tid >> 6;
-  // The bin comes from the ticket counter (bins are taken in the order
-  // workgroups start, which the chained scan's waits rely on). Workgroups
-  // almost always start in index order, so the bin of this workgroup's
-  // index is read while the ticket is fetched, and read again only if the
-  // ticket names another bin.
+  // The bin comes from the ticket counter: bins are taken in the order
+  // workgroups start, so a workgroup's chained-scan waits are only for
+  // workgroups already running.
   if (tid == 0) s_b = atomicAdd(a.ticket, 1u) - a.ticket_base;
   // the thread's first kHeld pairs, all loaded before any is used and kept
   // for the second pass; a bin with more pairs reads the rest in place
@@ -438,7 +436,6 @@ __global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
       pr[i] = (!err && j < cnt) ? a.pairs[st + j] : 0ull;
     }
   };
-  read_bin(blockIdx.x);
   for (int w = tid; w < kBinWords; w += kReduceBlock) s_bits[w] = 0u;
   lds_barrier();
   const uint32_t ub = s_b;
@@ -447,7 +444,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_spmspv_reduce(ReduceArgs a) {
     return;
   }
   const int b = (int)ub;
-  if (b != (int)blockIdx.x) read_bin(b);
+  read_bin(b);
   if (!err) {
 #pragma unroll
     for (int i = 0; i < kHeld; ++i) {

@@ -292,6 +292,13 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
   unsigned long long* ctr_out = &st->ctr[k % 3];
   const int lane = lane_id();
   unsigned int my_reached = 0;
+  // (read as every workgroup starts, before the workgroups of this launch add
+  // their owners; either choice gives the same claims). After a push level
+  // the words of its vertices are written by its resolve, which runs in this
+  // level's mark kernel, after this one: then the visited word is needed.
+  const bool resolve_pending =
+      kin >= kLevelHist || (kin >= 1 && st->hist_mark[kin] == 1);
+  const bool visf = resolve_pending || (int64_t)st->reached * 4 >= nwords * 32;
 
   for (int64_t w = blockIdx.x; w < njt; w += gridDim.x) {
     const int64_t e0 = w * kTileJ;
@@ -361,9 +368,14 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
         vv[i] = col[s_qo[lo] + (e - s_qe[lo])];
       }
     }
+    // the visited word filters the word reads only once a quarter of the
+    // vertices is reached: before, nearly every target is unvisited and the
+    // word read would only add a step to the chain before the claim (the
+    // target's word alone tells a vertex of an earlier level: its word is
+    // smaller than the key)
     uint32_t vw[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) vw[i] = vv[i] >= 0 ? vis[vv[i] >> 5] : 0xFFFFFFFFu;
+    for (int i = 0; i < ITEMS; ++i) vw[i] = (visf && vv[i] >= 0) ? vis[vv[i] >> 5] : 0u;
     unsigned long long cur[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i)

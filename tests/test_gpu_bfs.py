@@ -39,6 +39,28 @@ def test_small_graphs_every_root(name, edges, n):
         assert_bfs_equal(g, G, r)
 
 
+def test_claim_level_after_push_level():
+    """A claim level that follows a push (mark-and-resolve) level runs before
+    that level's resolve writes its vertices' parent words, so its claims
+    must still treat those vertices as visited. R-MAT 16 without pull
+    levels and with a low vertex floor: the large levels push, the tail
+    levels claim."""
+    g = graphgen.rmat_csr(16, 16, 23)
+    G = graph_on_device(g)
+    deg = np.diff(g.off)
+    roots = np.random.default_rng(5).choice(np.nonzero(deg > 0)[0], 6, replace=False)
+    pairs = 0
+    for small in (-1, 8192):
+        G.set_options(pull_alpha=-1, claim=3, claim_min_frontier=256, small_frontier=small,
+                      profile=1)
+        for r in roots:
+            say(f"rmat16 push then claim, small_frontier {small}, root {r}")
+            assert_bfs_equal(g, G, int(r))
+            kinds = [L["mark"] for L in G.level_info() if L["frontier"] > 0]
+            pairs += sum(1 for a, b in zip(kinds, kinds[1:]) if a == 1 and b == 0)
+    assert pairs > 0
+
+
 def test_single_vertex():
     g = graphgen.from_edges(1, [])
     G = graph_on_device(g)

@@ -316,7 +316,9 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
     __syncthreads();
 
     if (cmark) {
-      // every edge to an unvisited target: min into its word, touch byte
+      // every edge to an unvisited target: min into its word (finish finds
+      // the level's vertices by their words; a touch byte per edge would
+      // cost as much again as the claims)
       int32_t vv[ITEMS];
       unsigned long long key[ITEMS];
 #pragma unroll
@@ -339,10 +341,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
       for (int i = 0; i < ITEMS; ++i) vw[i] = vv[i] >= 0 ? vis[vv[i] >> 5] : 0xFFFFFFFFu;
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i)
-        if (vv[i] >= 0 && !((vw[i] >> (vv[i] & 31)) & 1u)) {
-          atomicMin(rpl + vv[i], key[i]);
-          mark[vv[i]] = 1;
-        }
+        if (vv[i] >= 0 && !((vw[i] >> (vv[i] & 31)) & 1u)) atomicMin(rpl + vv[i], key[i]);
       __syncthreads();
       continue;
     }
@@ -489,8 +488,9 @@ __global__ __launch_bounds__(BLOCK) void k_expand(
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_finish(
     const int64_t* __restrict__ off, uint32_t* __restrict__ vis, uint8_t* __restrict__ mark,
-    Queues q, int32_t* __restrict__ jstart_base, int64_t njs, const int32_t* __restrict__ zq,
-    LevelState* st, int cbits, int64_t n, int64_t nwords, MarkPolicy mp, int hw,
+    const unsigned long long* __restrict__ rpl, Queues q, int32_t* __restrict__ jstart_base,
+    int64_t njs, const int32_t* __restrict__ zq, LevelState* st, int cbits, int64_t n,
+    int64_t n_active, int64_t nwords, MarkPolicy mp, int hw,
     const uint32_t* __restrict__ hot_new, int nslices, uint32_t* __restrict__ fbits) {
   __shared__ long long s_wc[BLOCK / 64], s_wd[BLOCK / 64];
   __shared__ unsigned long long s_base;
@@ -610,7 +610,34 @@ __global__ __launch_bounds__(BLOCK) void k_finish(
     const int64_t w = base + tid;
     uint32_t m = 0;
     uint32_t x[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    if (w < nwords) {
+    if (w < nwords && cmark) {
+      // a claim-touch level's vertices: the unvisited ones whose words hold
+      // this level (set by their claims); the word's 32 parent words are read
+      // only while some vertex of it is unvisited
+      const uint32_t vw = vis[w];
+      const int64_t vb = w << 5;
+      if (vw != 0xFFFFFFFFu && vb < n_active) {
+        uint32_t hit = 0;
+        if (vb + 32 <= n_active) {
+          const uint4* __restrict__ r4 = reinterpret_cast<const uint4*>(rpl + vb);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const uint4 t = r4[i];   // two words: high halves .y and .w hold the level
+            hit |= (t.y == (uint32_t)k ? 1u : 0u) << (2 * i);
+            hit |= (t.w == (uint32_t)k ? 1u : 0u) << (2 * i + 1);
+          }
+        } else {
+          for (int i = 0; i < (int)(n_active - vb); ++i)
+            hit |= ((uint32_t)(rpl[vb + i] >> 32) == (uint32_t)k ? 1u : 0u) << i;
+        }
+        m = hit & ~vw;
+        if (m) {
+          const uint4 a = mark4[2 * w], b = mark4[2 * w + 1];
+          x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+          x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+        }
+      }
+    } else if (w < nwords) {
       const uint4 a = mark4[2 * w], b = mark4[2 * w + 1];
       x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
       x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
@@ -1440,10 +1467,11 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
       mark_expand_launch(gm, st, a);
     }
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 3], st));
-    k_finish<kFinishBlock><<<gf, kFinishBlock, 0, st>>>(koff, c.vis, c.mark, q, c.jstart,
-                                                        c.njstart, c.zq, c.state, c.cbits, c.n,
-                                                        c.nwords, mp, c.hot_words, c.hot_new,
-                                                        gm, c.upper ? c.fbits : nullptr);
+    k_finish<kFinishBlock><<<gf, kFinishBlock, 0, st>>>(koff, c.vis, c.mark, c.rpl, q,
+                                                        c.jstart, c.njstart, c.zq, c.state,
+                                                        c.cbits, c.n, n_active, c.nwords, mp,
+                                                        c.hot_words, c.hot_new, gm,
+                                                        c.upper ? c.fbits : nullptr);
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 4], st));
     return BFS_OK;
   };

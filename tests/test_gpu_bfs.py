@@ -61,6 +61,26 @@ def test_claim_level_after_push_level():
     assert pairs > 0
 
 
+def test_claim_touch_levels_match_oracle():
+    """Large claim levels of a symmetric graph claim without touch bytes;
+    finish finds their vertices by the level in their parent words. ER
+    scale 20 with 2 edges per vertex: its degree-ordered copy's active
+    vertices end inside a 32-vertex word (19,098 isolated vertices), and
+    with mark levels off the large levels are claim-touch levels."""
+    g = graphgen.er_csr(20, 2, 41)
+    deg = np.diff(g.off)
+    assert (deg == 0).sum() % 32 != 0
+    G = graph_on_device(g)
+    G.set_options(claim_threshold=1 << 30, pull_alpha=-1, profile=1)
+    roots = np.random.default_rng(3).choice(np.nonzero(deg > 0)[0], 3, replace=False)
+    kinds = set()
+    for r in roots:
+        say(f"er20 claim-touch root {r}")
+        assert_bfs_equal(g, G, int(r))
+        kinds |= {L["mark"] for L in G.level_info() if L["frontier"] > 0}
+    assert 3 in kinds
+
+
 def test_single_vertex():
     g = graphgen.from_edges(1, [])
     G = graph_on_device(g)

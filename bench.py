@@ -61,8 +61,8 @@ def log(msg: str) -> None:
 
 # ------------------------------------------------------------- byte counts
 # Algorithmic bytes per level, from a search's per-level record (one dict per
-# launched level: mark = 0 claim, 1 push mark, 2 pull, 3 claim collected by
-# touch marks, 4 claim level run by the device level loop; frontier/edges = the level's input frontier and its
+# launched level: mark = 0 claim, 1 push mark, 2 pull, 3 claim-touch claim
+# level (collected by the level in the parent words), 4 claim level run by the device level loop; frontier/edges = the level's input frontier and its
 # adjacencies; pull_candidates/pull_edges = a pull level's searchers and the
 # adjacencies they examined, or a push mark level's resolved vertices and the
 # adjacencies their searches examined). "new" is the next level's input
@@ -84,8 +84,8 @@ def claim_bytes(levels, nwords: int) -> float:
     (the target's visited bit); per input frontier vertex 20 B (its queue
     entry: id, adjacency start, edge prefix); per vertex claimed 53 B (its
     packed word read and atomic min, 16 B; its two row offsets, 16 B; its queue
-    entry, 20 B; its tag, 1 B). Claim level collected by touch marks: per new
-    vertex 17 B (the atomic min of its word, its touch byte). Mark and pull
+    entry, 20 B; its tag, 1 B). Claim-touch level: per new vertex 16 B (the
+    atomic min of its word). Mark and pull
     levels: the level-(k-1) bitmap built from the tags over the whole
     graph, 32 B of tags read and 4 B written per bitmap word."""
     total = 0.0
@@ -95,7 +95,7 @@ def claim_bytes(levels, nwords: int) -> float:
         if L["mark"] in (1, 2):
             total += 36.0 * nwords
             continue
-        per_new = 17.0 if L["mark"] == 3 else 53.0
+        per_new = 16.0 if L["mark"] == 3 else 53.0
         total += 4.125 * L["edges"] + 20.0 * L["frontier"] + per_new * _new(levels, i)
     return total
 
@@ -130,18 +130,24 @@ def pull_bytes(levels, n_active: int) -> float:
     return total
 
 
-def finish_bytes(levels, nwords: int) -> float:
+def finish_bytes(levels, nwords: int, n_active: int | None = None) -> float:
     """k_finish. Claim level: per new vertex its queue id read and the atomic
     OR of its visited word (12 B); a large claim level (new frontier at
     least n/64) instead rebuilds the bitmap from the tags, 32 B read and 4 B
-    written per word. Mark, pull and touch-mark claim levels: the tags of the
-    whole graph (32 B per word) read; per new vertex its tag and visited bit
-    rewritten with its word (1 B + 1/8 B), and its two row offsets and queue
-    entry (36 B) unless the level pulls and so does the next one (no queue
-    is built then)."""
+    written per word. Mark and pull levels: the tags of the whole graph (32 B
+    per word) read. Claim-touch levels: the visited bitmap (4 B per word),
+    the parent word of every vertex of positive degree not visited before the
+    level (8 B), and the tags of the words that hold a new vertex (32 B per
+    word, at most one word per new vertex). Then on all three: per new vertex
+    its tag and visited bit rewritten with its word (1 B + 1/8 B), and its
+    two row offsets and queue entry (36 B) unless the level pulls and so does
+    the next one (no queue is built then)."""
     total = 0.0
     n = nwords * 32
+    n_act = n if n_active is None else n_active
+    seen = 0   # vertices visited before the level (the input frontiers so far)
     for i, L in enumerate(levels):
+        seen += L["frontier"]
         if L["frontier"] == 0 or L["mark"] == 4:
             continue
         new = _new(levels, i)
@@ -150,7 +156,11 @@ def finish_bytes(levels, nwords: int) -> float:
             continue
         next_pulls = i + 1 < len(levels) and levels[i + 1]["mark"] == 2
         queue = 0.0 if (L["mark"] == 2 and next_pulls) else 36.0
-        total += 32.0 * nwords + (1.125 + queue) * new
+        if L["mark"] == 3:
+            scan = 4.0 * nwords + 8.0 * max(n_act - seen, 0) + 32.0 * min(nwords, new)
+        else:
+            scan = 32.0 * nwords
+        total += scan + (1.125 + queue) * new
     return total
 
 
@@ -178,7 +188,7 @@ def examined_bytes(levels, n: int, n_active: int) -> float:
     """Whole-BFS bytes the levels examined (the sum of the kernels above)."""
     nwords = (n + 31) // 32
     return (claim_bytes(levels, nwords) + mark_expand_bytes(levels)
-            + pull_bytes(levels, n_active) + finish_bytes(levels, nwords)
+            + pull_bytes(levels, n_active) + finish_bytes(levels, nwords, n_active)
             + small_levels_bytes(levels) + init_out_bytes(n, n_active, nwords))
 
 
@@ -291,7 +301,7 @@ def kernel_split(stats, levels, n: int, n_active: int):
         kms["k_expand_mark"] += st.mark_ms + st.pull_ms
         kb["k_expand"] += claim_bytes(lv, nwords)
         kms["k_expand"] += st.expand_ms - st.mark_ms - st.pull_ms
-        kb["k_finish"] += finish_bytes(lv, nwords)
+        kb["k_finish"] += finish_bytes(lv, nwords, n_active)
         kms["k_finish"] += st.finish_ms
         kb["k_small_levels"] += small_levels_bytes(lv)
         kms["k_small_levels"] += st.small_ms

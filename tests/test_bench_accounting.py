@@ -32,7 +32,7 @@ LEVELS = [
 def test_claim_bytes_by_level_kind():
     nwords = 1 << 15          # the whole bitmap, not its LDS-resident prefix
     want = (4.125 * 10 + 20 * 1 + 53 * 10          # claim level, 10 vertices claimed
-            + 4.125 * 1000 + 20 * 10 + 17 * 500    # touch-mark claim level
+            + 4.125 * 1000 + 20 * 10 + 16 * 500    # claim-touch level: the atomic min
             + 36 * nwords + 36 * nwords             # mark levels: the level bitmap build
             + 4.125 * 800 + 20 * 700 + 0)          # last claim level, nothing new
     assert bench.claim_bytes(LEVELS, nwords) == pytest.approx(want)
@@ -57,8 +57,12 @@ def test_searches_decided_in_the_head_entry_add_no_row_bytes():
 
 def test_finish_bytes_by_level_kind():
     nwords = 1 << 15
+    n = nwords * 32
     want = (12 * 10                                 # claim level: visited bit per new vertex
-            + 32 * nwords + 37.125 * 500           # touch-mark claim: collected from the tags
+            # claim-touch level: visited words, the parent words of the
+            # vertices not visited before it (root + 10), tags of the words
+            # with new vertices
+            + 4 * nwords + 8 * (n - 11) + 32 * 500 + 37.125 * 500
             + 32 * nwords + 37.125 * 2000          # push mark level
             + 32 * nwords + 37.125 * 700           # pull level
             + 0)                                   # last claim level reached nothing
@@ -73,11 +77,23 @@ def test_finish_bytes_by_level_kind():
         32 * nwords + 1.125 * 400 + 32 * nwords + 37.125 * 3)
 
 
+def test_claim_touch_finish_reads_the_parent_words_of_the_unvisited_active_vertices():
+    nwords = 1 << 10
+    lv = [lvl(0, 1, 40), lvl(0, 40, 3000), lvl(3, 2000, 90000), lvl(0, 5000, 100)]
+    seen = 1 + 40 + 2000
+    for n_active in (nwords * 32, 20000):
+        want = (12 * 40 + 36 * nwords           # claim levels (the second rebuilds the bitmap)
+                + 4 * nwords + 8 * (n_active - seen) + 32 * min(nwords, 5000)
+                + 37.125 * 5000
+                + 0)                           # the last claim level reached nothing
+        assert bench.finish_bytes(lv, nwords, n_active) == pytest.approx(want)
+
+
 def test_examined_bytes_is_the_sum_of_the_kernels_plus_init_and_output():
     n, n_active = 1 << 20, 700000
     nwords = n // 32
     want = (bench.claim_bytes(LEVELS, nwords) + bench.mark_expand_bytes(LEVELS)
-            + bench.pull_bytes(LEVELS, n_active) + bench.finish_bytes(LEVELS, nwords)
+            + bench.pull_bytes(LEVELS, n_active) + bench.finish_bytes(LEVELS, nwords, n_active)
             + 8 * n_active + 4 * nwords + 32 * nwords + 20 * n)
     assert bench.examined_bytes(LEVELS, n, n_active) == pytest.approx(want)
 

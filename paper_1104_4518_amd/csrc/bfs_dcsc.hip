@@ -62,6 +62,39 @@ __global__ void k_build_aux(const int32_t* __restrict__ jc, int32_t nzc, int shi
   }
 }
 
+// Bucket records: bucket b's stored columns in one 64-byte line (16 words):
+// [0] first position p, [1] count (bit 31: no record, use AUX/JC/CP),
+// [2] cp[p], [3..6] the columns' offsets in the bucket (one byte each, up to
+// kRecCols), [7..13] cp[p + i + 1] - cp[p] for each column i (16 bits each).
+constexpr int kRecCols = 14;
+__global__ void k_build_recs(const int32_t* __restrict__ jc, const int32_t* __restrict__ cp,
+                             const int32_t* __restrict__ aux, int shift, int64_t nb,
+                             uint4* __restrict__ recs) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb; b += stride) {
+    const int32_t lo = aux[b], cnt = aux[b + 1] - lo;
+    const int32_t base = cp[lo];
+    uint32_t w[16] = {0u};
+    bool ok = cnt <= kRecCols;
+    for (int i = 0; ok && i < cnt; ++i) {
+      const uint32_t off = (uint32_t)((int64_t)jc[lo + i] - (b << shift));
+      const int32_t cum = cp[lo + i + 1] - base;
+      if (cum > 0xFFFF) {
+        ok = false;
+        break;
+      }
+      w[3 + (i >> 2)] |= off << (8 * (i & 3));
+      w[7 + (i >> 1)] |= (uint32_t)cum << (16 * (i & 1));
+    }
+    w[0] = (uint32_t)lo;
+    w[1] = (uint32_t)cnt | (ok ? 0u : 0x80000000u);
+    w[2] = (uint32_t)base;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+      recs[b * 4 + x] = make_uint4(w[4 * x], w[4 * x + 1], w[4 * x + 2], w[4 * x + 3]);
+  }
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -130,6 +163,7 @@ struct BinArgs {
   const int32_t* cp;
   const int32_t* ir;
   const int32_t* aux;
+  const uint4* recs;        // bucket records, or null (buckets wider than 256 columns)
   int shift;
   int32_t nbins;
   const int64_t* bin_start;
@@ -227,7 +261,7 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
     const int nE = (int)min((int64_t)SUB, a.fnnz - c0);
     // lookup; every step issues the loads of all the thread's entries before
     // it uses any of them (entries without a column read index 0 and drop it)
-    int32_t kk[EPT], kv[EPT], lo[EPT], hi[EPT], bend[EPT];
+    int32_t kk[EPT], kv[EPT];
     {
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
@@ -244,85 +278,143 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
           kk[j] = -1;
         }
       }
+    }
+    // column positions. With one entry per thread (small frontiers, whose
+    // lookups are scattered) the entry's bucket record, one 64-byte line,
+    // holds the bucket's columns and their row ranges and so decides the
+    // lookup in one load. Other entries (larger frontiers, and buckets
+    // without a record) read AUX, then a bucket of JC (its first kProbe
+    // columns together for one entry per thread, else, and past them, a
+    // binary search), then CP.
+    int32_t q0[EPT], len[EPT];
+    bool slow[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      q0[j] = 0;
+      len[j] = 0;
+      slow[j] = kk[j] >= 0;
+    }
+    if constexpr (PROBE) {
+      if (a.recs) {
+        uint4 r[EPT][4];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+          const int64_t bk = kk[j] >= 0 ? ((int64_t)kk[j] >> a.shift) : 0;
+#pragma unroll
+          for (int x = 0; x < 4; ++x) r[j][x] = a.recs[bk * 4 + x];
+        }
+        // (an empty use of every loaded word, so that the compiler cannot
+        // load the count alone and the rest only under a branch on it)
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+            asm volatile("" ::"v"(r[j][x].x), "v"(r[j][x].y), "v"(r[j][x].z), "v"(r[j][x].w));
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+          const uint32_t w[16] = {r[j][0].x, r[j][0].y, r[j][0].z, r[j][0].w,
+                                  r[j][1].x, r[j][1].y, r[j][1].z, r[j][1].w,
+                                  r[j][2].x, r[j][2].y, r[j][2].z, r[j][2].w,
+                                  r[j][3].x, r[j][3].y, r[j][3].z, r[j][3].w};
+          if (kk[j] < 0 || (w[1] >> 31)) continue;
+          slow[j] = false;
+          const uint32_t off = (uint32_t)kk[j] & ((1u << a.shift) - 1u);
+#pragma unroll
+          for (int i = 0; i < kRecCols; ++i) {
+            const uint32_t col = (w[3 + (i >> 2)] >> (8 * (i & 3))) & 0xFFu;
+            const uint32_t c1 = (w[7 + (i >> 1)] >> (16 * (i & 1))) & 0xFFFFu;
+            const uint32_t c0 = i ? (w[7 + ((i - 1) >> 1)] >> (16 * ((i - 1) & 1))) & 0xFFFFu : 0u;
+            if ((uint32_t)i < w[1] && col == off) {
+              q0[j] = (int32_t)(w[2] + c0);
+              len[j] = (int32_t)(c1 - c0);
+            }
+          }
+        }
+      }
+    }
+    bool any_slow = false;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) any_slow |= slow[j];
+    if (__any(any_slow)) {
+      int32_t ks[EPT], lo[EPT], hi[EPT], bend[EPT], qp[EPT];
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        ks[j] = slow[j] ? kk[j] : -1;
+        qp[j] = -1;
+      }
       int32_t a0[EPT], a1[EPT];
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
-        const int64_t bk = kk[j] >= 0 ? ((int64_t)kk[j] >> a.shift) : 0;
+        const int64_t bk = ks[j] >= 0 ? ((int64_t)ks[j] >> a.shift) : 0;
         a0[j] = a.aux[bk];
         a1[j] = a.aux[bk + 1];
       }
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
-        lo[j] = kk[j] >= 0 ? a0[j] : 0;
-        hi[j] = bend[j] = kk[j] >= 0 ? a1[j] : 0;
+        lo[j] = ks[j] >= 0 ? a0[j] : 0;
+        hi[j] = bend[j] = ks[j] >= 0 ? a1[j] : 0;
       }
-    }
-    // column positions: with one entry per thread (small frontiers, whose
-    // lookups are scattered) the bucket's first kProbe stored columns are
-    // read together, which decides most lookups (buckets hold about four)
-    // in one step; otherwise, and past them, a binary search in the bucket
-    int32_t q0[EPT], len[EPT];
+      if constexpr (PROBE) {
+        int32_t w[EPT][kProbe];
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) q0[j] = -1;
-    if constexpr (PROBE) {
-      int32_t w[EPT][kProbe];
+        for (int j = 0; j < EPT; ++j)
 #pragma unroll
-      for (int j = 0; j < EPT; ++j)
+          for (int i = 0; i < kProbe; ++i) w[j][i] = a.jc[lo[j] + i < hi[j] ? lo[j] + i : 0];
 #pragma unroll
-        for (int i = 0; i < kProbe; ++i) w[j][i] = a.jc[lo[j] + i < hi[j] ? lo[j] + i : 0];
+        for (int j = 0; j < EPT; ++j) {
+          int c = 0;
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        int c = 0;
+          for (int i = 0; i < kProbe; ++i) c += lo[j] + i < hi[j] && w[j][i] < ks[j];
+          int32_t at = INT32_MAX;
 #pragma unroll
-        for (int i = 0; i < kProbe; ++i) c += lo[j] + i < hi[j] && w[j][i] < kk[j];
-        int32_t at = INT32_MAX;
-#pragma unroll
-        for (int i = kProbe - 1; i >= 0; --i)
-          if (i == c && lo[j] + i < hi[j]) at = w[j][i];
-        if (kk[j] >= 0 && c < kProbe && at == kk[j]) q0[j] = lo[j] + c;
-        if (kk[j] >= 0 && c == kProbe && lo[j] + kProbe < hi[j]) lo[j] += kProbe;
-        else lo[j] = hi[j];
-      }
-    }
-    for (;;) {
-      bool any = false;
-      int32_t mid[EPT], vm[EPT];
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        mid[j] = (lo[j] + hi[j]) >> 1;
-        vm[j] = a.jc[lo[j] < hi[j] ? mid[j] : 0];
-      }
-#pragma unroll
-      for (int j = 0; j < EPT; ++j)
-        if (lo[j] < hi[j]) {
-          if (vm[j] < kk[j]) lo[j] = mid[j] + 1; else hi[j] = mid[j];
-          any = true;
+          for (int i = kProbe - 1; i >= 0; --i)
+            if (i == c && lo[j] + i < hi[j]) at = w[j][i];
+          if (ks[j] >= 0 && c < kProbe && at == ks[j]) qp[j] = lo[j] + c;
+          if (ks[j] >= 0 && c == kProbe && lo[j] + kProbe < hi[j]) lo[j] += kProbe;
+          else lo[j] = hi[j];
         }
-      if (!any) break;
-    }
-    {
-      int32_t vl[EPT];
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const bool open = q0[j] < 0 && kk[j] >= 0 && lo[j] < bend[j];
-        vl[j] = a.jc[open ? lo[j] : 0];
       }
+      for (;;) {
+        bool any = false;
+        int32_t mid[EPT], vm[EPT];
 #pragma unroll
-      for (int j = 0; j < EPT; ++j)
-        if (q0[j] < 0 && kk[j] >= 0 && lo[j] < bend[j] && vl[j] == kk[j]) q0[j] = lo[j];
-    }
-    {
-      int32_t c0[EPT], c1[EPT];
+        for (int j = 0; j < EPT; ++j) {
+          mid[j] = (lo[j] + hi[j]) >> 1;
+          vm[j] = a.jc[lo[j] < hi[j] ? mid[j] : 0];
+        }
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const int32_t p = q0[j] >= 0 ? q0[j] : 0;
-        c0[j] = a.cp[p];
-        c1[j] = a.cp[p + 1];
+        for (int j = 0; j < EPT; ++j)
+          if (lo[j] < hi[j]) {
+            if (vm[j] < ks[j]) lo[j] = mid[j] + 1; else hi[j] = mid[j];
+            any = true;
+          }
+        if (!any) break;
       }
+      {
+        int32_t vl[EPT];
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        len[j] = q0[j] >= 0 ? c1[j] - c0[j] : 0;
-        q0[j] = q0[j] >= 0 ? c0[j] : 0;
+        for (int j = 0; j < EPT; ++j) {
+          const bool open = qp[j] < 0 && ks[j] >= 0 && lo[j] < bend[j];
+          vl[j] = a.jc[open ? lo[j] : 0];
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          if (qp[j] < 0 && ks[j] >= 0 && lo[j] < bend[j] && vl[j] == ks[j]) qp[j] = lo[j];
+      }
+      {
+        int32_t c0[EPT], c1[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+          const int32_t p = qp[j] >= 0 ? qp[j] : 0;
+          c0[j] = a.cp[p];
+          c1[j] = a.cp[p + 1];
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          if (slow[j] && qp[j] >= 0) {
+            len[j] = c1[j] - c0[j];
+            q0[j] = c0[j];
+          }
       }
     }
     int mine = 0;
@@ -827,6 +919,13 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   d.naux = ((int64_t)std::max(d.ncols, 1) >> shift) + 2;
   BFS_HIP(hipMalloc(&d.aux, (size_t)d.naux * 4));
   k_build_aux<<<1024, 256, 0, s>>>(d.jc, d.nzc, shift, d.naux, d.aux);
+  // bucket records (one byte per column offset: buckets of at most 256 columns)
+  d.recs = nullptr;
+  if (shift <= 8) {
+    BFS_HIP(hipMalloc(&d.recs, (size_t)(d.naux - 1) * 64));
+    k_build_recs<<<1024, 256, 0, s>>>(d.jc, d.cp, d.aux, shift, d.naux - 1,
+                                      reinterpret_cast<uint4*>(d.recs));
+  }
   // row bins: each owns a slice of the pair buffer as long as its stored entries
   d.nbins = (int32_t)(((int64_t)std::max(d.nrows, 1) + kBinRows - 1) >> kBinShift);
   BFS_HIP(hipMalloc(&d.bin_start, (size_t)(d.nbins + 1) * 8));
@@ -878,7 +977,8 @@ int dcsc_setup(bfs_graph* g, hipStream_t s, bool validate) {
   (void)hipGetLastError();
   d.grid_bin = cus * occ;   // co-resident workgroups of the binning kernel
   d.epoch = 1;
-  g->device_bytes += d.naux * 4 + (int64_t)std::max(d.nrows, 1) * 4 +
+  g->device_bytes += d.naux * 4 + (d.recs ? (d.naux - 1) * 64 : 0) +
+                     (int64_t)std::max(d.nrows, 1) * 4 +
                      (int64_t)(d.nbins + 1) * 8 + (int64_t)d.nbins * 12 + 4 +
                      std::max<int64_t>(d.nnz, 1) * 8 + 32;
   return BFS_OK;
@@ -890,6 +990,7 @@ void dcsc_free(bfs_graph* g) {
   (void)hipFree(d.cp);
   (void)hipFree(d.ir);
   (void)hipFree(d.aux);
+  if (d.recs) (void)hipFree(d.recs);
   (void)hipFree(d.spa_val);
   (void)hipFree(d.bin_start);
   (void)hipFree(d.cursor);
@@ -952,6 +1053,7 @@ int dcsc_spmspv(bfs_graph* g, const bfs_svec_t* f, bfs_svec_t* out, hipStream_t 
   ba.cp = d.cp;
   ba.ir = d.ir;
   ba.aux = d.aux;
+  ba.recs = reinterpret_cast<const uint4*>(d.recs);
   ba.shift = d.aux_shift;
   ba.nbins = d.nbins;
   ba.bin_start = d.bin_start;

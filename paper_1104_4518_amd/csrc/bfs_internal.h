@@ -158,6 +158,7 @@ struct DcscDev {
   int aux_shift = 0;             // column bucket width = 2^aux_shift
   int64_t naux = 0;
   int32_t* aux = nullptr;        // aux[b] = first p with jc[p] >= b << aux_shift
+  uint32_t* recs = nullptr;      // 16 words per bucket (see k_build_recs), or null
   // binned product: rows in bins of 2^18, bin b's products in
   // pairs[bin_start[b] .. bin_start[b + 1]) ((row in bin) << 32 | value)
   int32_t nbins = 0;

@@ -8,7 +8,9 @@
 //   binned accumulator (any frontier): the sparse accumulator of section 4.2
 //            split by rows. k_spmspv_bin looks up each frontier index k in JC
 //            (a bucket index over column ids, aux[b] = first p with JC[p] >=
-//            b * width, then a short search), expands the rows IR[CP[p] ..
+//            b * width, then a short search; for scattered lookups a record
+//            per bucket holds its columns and row ranges in one line),
+//            expands the rows IR[CP[p] ..
 //            CP[p+1]) edge-balanced and appends every (row, value) product to
 //            the bin of its row (2^18 rows per bin); k_spmspv_reduce gives
 //            every bin one workgroup, whose LDS holds the bin's accumulator
@@ -107,8 +109,8 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
 // entries of the block in those rows (a bound on the products one call can
 // put there, since every stored entry yields at most one product).
 //
-//   k_spmspv_bin     looks up the frontier's columns (bucket index + short
-//                    search), expands them edge-balanced, and
+//   k_spmspv_bin     looks up the frontier's columns (bucket record, or
+//                    bucket index + short search), expands them edge-balanced, and
 //                    appends every product (row, value) to its row's bin:
 //                    products are staged in LDS, counted per bin, and each
 //                    workgroup reserves its slots of a bin with one atomic

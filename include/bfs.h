@@ -239,7 +239,8 @@ int bfs_last_stats(bfs_graph_t* g, bfs_run_stats_t* st);
 typedef struct bfs_level_info {
   int32_t level;        /* k: the level whose vertices this step discovered */
   int32_t mark;         /* 1 = mark-and-resolve, 2 = pull (by rows), 0 = atomicMin claims,
-                           3 = atomicMin claims collected by touch marks (large claim level),
+                           3 = atomicMin claims collected afterwards in vertex order (large
+                               claim level),
                            4 = atomicMin claims inside the device level loop */
   int64_t frontier;     /* vertices of frontier k-1 that were expanded */
   int64_t edges;        /* their adjacencies */

@@ -36,7 +36,9 @@
 //   finish(k)  claim levels: sets the visited bits of the new frontier.
 //              mark levels: collects the touched vertices one 32-vertex word
 //              per thread, appends them to the next frontier, sets their
-//              visited bits and gives them the level's tag.
+//              visited bits and gives them the level's tag; large claim
+//              levels whose claims were not waited for are collected the
+//              same way, their vertices found by the level in their words.
 //   resolve(k) push mark levels: gives each vertex of the new frontier its
 //              level and its parent, the first neighbour one level up in
 //              its ascending adjacency list (for an undirected graph that is

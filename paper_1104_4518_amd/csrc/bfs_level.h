@@ -72,8 +72,8 @@ __device__ __forceinline__ bool mark_level(unsigned long long cin, int cbits,
 // 1/64 of the adjacencies spread over many vertices (at most 128 per
 // frontier vertex on average, so most targets are new and reached once):
 // every edge to an unvisited target does a 64-bit atomicMin whose result is
-// not waited for and stores the touch byte; finish then collects the touched
-// vertices in vertex order as on mark levels, with the parents already
+// not waited for; finish then collects the level's vertices in vertex order,
+// as on mark levels, by the level in their words, with the parents already
 // final. Saves the per-edge ownership test and appends. A frontier of a few
 // hubs instead reaches each target many times, and there the claim's plain
 // read before the atomic filters most of them.

@@ -1406,6 +1406,11 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   // the device level loop for small frontiers (not for upper-triangle
   // graphs, whose levels also need the reverse search)
   const bool small_on = !c.upper && g->opt.small_frontier >= 0;
+  // whether the launch groups being enqueued start with the loop: in mode 1
+  // only while the frontier last read by the host was small enough for it
+  // (a batch after a large frontier would mostly launch it for nothing; its
+  // small levels then run through the level kernels until the next read)
+  bool loop_now = small_on;
   SmallArgs sa;
   sa.off = koff;
   sa.col = kcol;
@@ -1431,14 +1436,14 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
   // level's resolve | finish).
   auto enqueue_group = [&](hipStream_t st, int64_t ev_base) -> int {
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base], st));
-    if (small_on) small_levels_launch(st, sa);
+    if (loop_now) small_levels_launch(st, sa);
     if (ev_base >= 0) BFS_HIP(hipEventRecord(g->ev[(size_t)ev_base + 1], st));
     k_expand<kExpandBlock><<<ge, kExpandBlock, 0, st>>>(koff, kcol, c.vis, c.rpl,
                                                         c.mark, q, c.jstart, c.njstart, c.zq,
                                                         c.state, c.cbits, mp, kinv,
                                                         c.nwords, c.prev_bits,
                                                         c.upper ? c.fbits : nullptr,
-                                                        small_on ? 0 : 1);
+                                                        loop_now ? 0 : 1);
     if (c.upper)
       k_reverse<kRevBlock><<<gf, kRevBlock, 0, st>>>(koff, kcol, c.vis, c.rpl, c.fbits, q,
                                                      c.jstart, c.njstart, c.zq, c.state,
@@ -1497,6 +1502,8 @@ int csr_run(bfs_graph* g, int32_t root, int32_t* parent, int32_t* level, hipStre
     unsigned int z = 0;
     std::memcpy(&ctr, head + offsetof(LevelState, ctr) + 8 * ((kx - 1) % 3), 8);
     std::memcpy(&z, head + offsetof(LevelState, zcnt) + 4 * ((kx - 1) % 3), 4);
+    loop_now = small_on && (int64_t)(ctr & cmask) <= sa.max_f &&
+               (int64_t)(ctr >> c.cbits) <= sa.max_t;
     if (ctr & cmask) return 1;
     // rowless frontier vertices of an upper-triangle graph
     return (c.upper && z > 0) ? 1 : 0;

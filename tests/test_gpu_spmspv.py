@@ -223,3 +223,36 @@ def test_sort_path_limits_and_fallback():
         say(f"fallback product rep {rep}")
         check(Gd, bd, f, fv)
         check(Gd, bd, f[:2])
+
+
+def test_buckets_without_a_record_fall_back_to_the_column_search():
+    """Scattered lookups read a record per bucket of columns; a bucket with
+    more stored columns than a record holds, or with a column longer than its
+    16-bit row counts, has none and is searched in AUX, JC and CP, in the same
+    waves as entries whose buckets have records. Here the buckets span 64
+    columns: bucket 0 stores all 64, bucket 1 holds a column of 70,000 rows,
+    the rest are sparse; small frontiers mix all three kinds."""
+    rng = np.random.default_rng(71)
+    nr, nc = 1 << 17, 1 << 16
+    cols = set(range(64)) | {100}
+    cols |= set(rng.choice(np.arange(128, nc), 2000, replace=False).tolist())
+    jc = np.array(sorted(cols), np.int32)
+    rows = []
+    for c in jc:
+        k = 70000 if c == 100 else int(rng.integers(1, 8))
+        rows.append(np.sort(rng.choice(nr, k, replace=False)).astype(np.int32))
+    cp = np.zeros(len(jc) + 1, np.int32)
+    cp[1:] = np.cumsum([len(r) for r in rows])
+    blk = graphgen.DCSCBlock(nr, nc, jc, cp, np.concatenate(rows))
+    Gb = block_on_device(blk, -1)
+    stored = jc.astype(np.int64)
+    for seed in range(4):
+        r2 = np.random.default_rng(100 + seed)
+        pick = set(r2.choice(64, 10, replace=False).tolist()) | {100}
+        pick |= set(r2.choice(stored, 300, replace=False).tolist())
+        pick |= set(r2.choice(nc, 100, replace=False).tolist())   # some on empty columns
+        fidx = np.array(sorted(pick), np.int32)
+        fval = r2.integers(-(1 << 30), 1 << 30, len(fidx)).astype(np.int32) if seed % 2 else None
+        say(f"record fallback frontier {len(fidx)} seed {seed}")
+        check(Gb, blk, fidx, fval)
+    check(Gb, blk, jc.copy())   # every stored column
